@@ -1,0 +1,42 @@
+"""Closed forms of the anisotropy analysis and the adaptive step (FP64 numpy).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+  aabb_volume_ratio  Vol(AABB(E)) / Vol(E) = (6/pi) sqrt(prod_i sum_j r_ij^2 s_j^2) / (s1 s2 s3)
+                     (Sec. 3.4, Eq. 6; Supp. B, derivation of the ratio)
+  ratio_bound        2/(pi sqrt 3) (s1^2+s2^2+s3^2)^(3/2) / (s1 s2 s3)
+                     (Sec. 3.4, Eq. 7 and Eq. 9; Supp. B, upper bound)
+  isotropic_loss     mean over Gaussians of max(r_max, r0) - r0 (Sec. 3.4, Eq. 8)
+  adaptive_step      min(max(d/beta, dt_min) * T^(-1/3), dt_max) (Sec. 3.2, Eq. 5; the
+                     segment is N_S times this)
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def aabb_volume_ratio(R, s):
+    R = np.asarray(R, np.float64)
+    s = np.asarray(s, np.float64)
+    l = np.einsum("...ij,...j->...i", R * R, s * s)
+    return 6.0 / math.pi * np.sqrt(np.prod(l, axis=-1)) / np.prod(s, axis=-1)
+
+
+def ratio_bound(s):
+    s = np.asarray(s, np.float64)
+    return 2.0 / (math.pi * math.sqrt(3.0)) * np.sum(s * s, axis=-1) ** 1.5 / np.prod(s, axis=-1)
+
+
+def isotropic_loss(log_scales, r0=10.0):
+    r = ratio_bound(np.exp(np.asarray(log_scales, np.float64)))
+    return float(np.mean(np.maximum(r, r0) - r0))
+
+
+def adaptive_step(d, T, dt_min=0.005, dt_max=0.02, beta=1024.0):
+    d = np.asarray(d, np.float64)
+    T = np.asarray(T, np.float64)
+    with np.errstate(divide="ignore"):
+        v = np.maximum(d / beta, dt_min) * T ** (-1.0 / 3.0)
+    return np.minimum(v, dt_max)
