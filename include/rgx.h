@@ -1,0 +1,189 @@
+/*
+ * rgx.h -- C ABI of the MI355X (gfx950) library for differentiable volume ray
+ * marching through truncated anisotropic Gaussians found via a BVH
+ * (RayGaussX, arXiv 2509.07782).
+ *
+ * The method: a scene of N Gaussians defines a density field
+ *   sigma(x) = sum_l sigma~_l exp(-q_l(x)/2) [q_l(x) <= k_l^2],
+ *   q_l(x) = (x-mu_l)^T Sigma_l^-1 (x-mu_l), Sigma_l = R_l S_l S_l^T R_l^T,
+ *   k_l^2 = 2 ln(sigma~_l / sigma_eps)                    (Sec. 3.1 Eq. 1; Supp. B)
+ * and a radiance field equal to the density-weighted mean of per-Gaussian
+ * spherical-harmonic colours c_l(d) at the ray direction (Eq. 1).  A pixel is
+ * the discrete volume-rendering sum of Eq. 3 evaluated segment by segment as in
+ * Algorithm 1 (Sec. 3.2): N_s midpoint samples per segment, empty-space
+ * skipping through closest-hit queries (Eq. 4), optional adaptive segment size
+ * (Eq. 5) and early termination when the transmittance drops to T_eps.
+ *
+ * Conventions shared by every call
+ *  - Pointers are DEVICE pointers unless marked (host).  The caller owns every
+ *    buffer it passes; the library keeps no pointer to a caller buffer after a
+ *    call returns.
+ *  - Every call is asynchronous and ordered on the given hipStream_t (NULL is
+ *    the default stream).  No call synchronises the host except where stated.
+ *  - Parameter arrays are float32, contiguous, row-major, in the caller's
+ *    ("user") Gaussian order.  Quaternions are (w,x,y,z) of any non-zero norm;
+ *    scales are given as log-scales l (s = exp(l)); density is the raw
+ *    sigma~ (no activation); sh is [n, K, 3] with K = (deg+1)^2, real SH basis
+ *    with the Condon-Shortley phase, index l^2+l+m, evaluated at the unit ray
+ *    direction, colour used as is (no offset or clamp).
+ *  - Rays: pinhole through the pixel centre (u+1/2, v+1/2), pixel (0,0) top
+ *    left, camera axes x right / y down / z forward, unit direction so that t
+ *    is metric distance from the camera centre.  Output pixels of view v are
+ *    row-major and views are concatenated in order.
+ *  - Errors: host-detectable errors return a negative rgx_status before
+ *    anything is enqueued.  Data-dependent cases are not errors: a Gaussian
+ *    with sigma~ <= sigma_eps, a zero quaternion or a non-finite parameter is
+ *    inactive (never hit, zero gradient).  HIP failures return RGX_ERR_HIP with
+ *    the HIP message in rgx_last_error().
+ */
+#ifndef RGX_H
+#define RGX_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RGX_OK = 0,
+  RGX_ERR_INVALID_ARG = -1,
+  RGX_ERR_OUT_OF_MEMORY = -2,
+  RGX_ERR_HIP = -3,
+  RGX_ERR_UNSUPPORTED = -4,
+  RGX_ERR_STATE = -5
+} rgx_status;
+
+/* Library context: owns the device workspace and the per-device launch
+   parameters.  One context per stream/thread at a time. */
+typedef struct rgx_context rgx_context;
+
+/* Acceleration structure built from one set of Gaussian parameters: the
+   Z-ordered (Morton-sorted, Sec. 3.3) copy of the per-Gaussian geometry and
+   colour records, the permutation to user order and the LBVH over the
+   ellipsoids' minimal AABBs (Supp. B).  Rebuilding reuses its memory. */
+typedef struct rgx_bvh rgx_bvh;
+
+typedef struct {
+  int64_t n;                 /* number of Gaussians, >= 1 */
+  int32_t sh_degree;         /* 0..3 */
+  const float *means;        /* [n,3] mu */
+  const float *log_scales;   /* [n,3] l */
+  const float *quats;        /* [n,4] (w,x,y,z) */
+  const float *density;      /* [n]   sigma~ */
+  const float *sh;           /* [n,K,3] */
+} rgx_gaussians;
+
+typedef struct {
+  float sigma_eps;           /* density threshold of the truncation ellipsoid, > 0 (default 0.01) */
+  int32_t morton_bits;       /* bits per axis of the Z-order key, 1..21 (default 21) */
+} rgx_build_opts;
+
+typedef struct {             /* (host) pinhole camera */
+  int32_t width, height;     /* > 0 */
+  float fx, fy, cx, cy;      /* intrinsics in pixels */
+  float cam_to_world[12];    /* 3x4 row-major [R | centre]; R columns = camera x, y, z in world */
+  float t_near, t_far;       /* integration bounds along the ray, 0 <= t_near < t_far */
+} rgx_camera;
+
+typedef struct {
+  int32_t adaptive;          /* 0: fixed step dt; 1: Eq. 5 step from dt_min, dt_max, beta */
+  float dt, dt_min, dt_max, beta;
+  int32_t n_s;               /* samples per segment N_s: 1, 2, 4, 8 or 16 */
+  float t_eps;               /* transmittance threshold T_eps >= 0, tested at segment starts */
+  int32_t ess;               /* empty-space skipping: 0 off; 1 restart snapped to the segment
+                                grid (fixed step; image identical to 0); 2 restart at the
+                                closest hit itself (the only form used in adaptive mode) */
+  int32_t brute_force;       /* 1: test every Gaussian instead of the BVH (hit-set reference) */
+  int32_t ray_order;         /* 0: scanline rows of 64 rays; 1: tiles in Morton order */
+  int32_t tile_w, tile_h;    /* tile shape for ray_order 1, tile_w*tile_h = 64 (0: 8x8) */
+  int32_t persistent;        /* 1: persistent launch popping tiles from a device queue */
+  float bg[3];               /* background colour added with the final transmittance */
+} rgx_render_opts;
+
+typedef struct {             /* gradient outputs, user order, float32 */
+  float *means, *log_scales, *quats, *density, *sh;  /* [n,3] [n,3] [n,4] [n] [n,K,3] */
+  int32_t accumulate;        /* 0: overwrite, 1: add into the buffers */
+} rgx_grads;
+
+/* per-ray statistics written by rgx_render_forward when `stats` is given */
+enum {
+  RGX_STAT_Q = 0,        /* distinct Gaussians in the hit sets of processed segments */
+  RGX_STAT_P,            /* (segment, Gaussian) pairs over processed segments */
+  RGX_STAT_SAMPLES,      /* samples evaluated (t < t_far, non-empty segments) */
+  RGX_STAT_SEGMENTS,     /* non-empty segments processed */
+  RGX_STAT_CLOSEST,      /* closest-hit queries */
+  RGX_STAT_BOX_ONLY,     /* leaves whose AABB met the segment but whose ellipsoid did not */
+  RGX_NSTAT = 8
+};
+
+/* Create / destroy a context on HIP device `device`.  rgx_create allocates. */
+rgx_status rgx_create(int device, rgx_context **out);
+void rgx_destroy(rgx_context *ctx);
+
+/* Build (or rebuild in place when *bvh is non-NULL) the acceleration
+   structure: per-Gaussian preprocessing (R from the normalised quaternion,
+   s = exp(l), M = S^-1 R^T, k^2 = 2 ln(sigma~/sigma_eps), minimal AABB
+   half-lengths L_i = k sqrt(sum_j r_ij^2 s_j^2) padded outward), Morton keys
+   of the means quantised over their bounds (Sec. 3.3), a stable radix sort,
+   the Z-ordered pack and a Karras LBVH with bottom-up refit.  Allocates device
+   memory when the structure must grow (never during stream capture).  The
+   parameters are copied; the caller may change them afterwards. */
+rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_build_opts *opts,
+                         rgx_bvh **bvh, hipStream_t stream);
+void rgx_bvh_destroy(rgx_bvh *bvh);
+/* (host) number of Gaussians and SH degree the structure was built from */
+int64_t rgx_bvh_size(const rgx_bvh *bvh);
+
+/* Forward render of n_views views (host array) through Algorithm 1.
+   out_rgb [R,3] and out_T [R] with R = sum of width*height; `stats`
+   (nullable) receives [R, RGX_NSTAT] int32 counters. */
+rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
+                              int32_t n_views, const rgx_render_opts *opts, float *out_rgb,
+                              float *out_T, int32_t *stats, hipStream_t stream);
+
+/* Backward of rgx_render_forward: given the forward outputs (out_rgb, out_T
+   exactly as returned) and dL/d(out_rgb) [R,3], dL/d(out_T) [R] (nullable),
+   writes dL/d(parameters) in user order.  The sample schedule, the ESS
+   restarts and the truncation boundaries are treated as constants.  The
+   segments are re-traversed in the forward's deterministic order; the
+   transmittance before every sample is recomputed, and the colour still to
+   come behind a sample is the final colour minus the running prefix. */
+rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
+                               int32_t n_views, const rgx_render_opts *opts, const float *out_rgb,
+                               const float *out_T, const float *grad_rgb, const float *grad_T,
+                               const rgx_grads *grads, hipStream_t stream);
+
+/* Debug: per-ray hit sets.  For the rays `pix` (row-major pixel indices of
+   the single view `cam`), records every (segment start, Gaussian) pair of
+   every processed segment in processing order: seg_a [n_rays, cap] float,
+   ids [n_rays, cap] int32 user-order Gaussian ids, count [n_rays] the number
+   of pairs (entries beyond cap are counted but not written). */
+rgx_status rgx_dump_hits(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cam,
+                         const rgx_render_opts *opts, const int32_t *pix, int32_t n_rays,
+                         int32_t cap, float *seg_a, int32_t *ids, int32_t *count,
+                         hipStream_t stream);
+
+/* Debug: copies of the build's internal arrays for structure checks
+   (synchronises the stream).  Any output may be NULL.
+     keys  [n] uint64 sorted Morton keys (inactive Gaussians last, key 2^(3*bits))
+     perm  [n] int32  user index of the i-th Z-ordered Gaussian
+     aabb  [n,6] float leaf boxes (lo xyz, hi xyz) in Z order
+     nodes [max(n-1,1), 16] float internal nodes: left box lo/hi, right box lo/hi,
+           children as int bits (>= 0 internal, < 0 leaf ~i, INT32_MIN none)
+     n_active (host) number of active Gaussians. */
+rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *bvh, uint64_t *keys, int32_t *perm,
+                         float *aabb, float *nodes, int64_t *n_active, hipStream_t stream);
+
+/* Debug: device-side error flags of the context (synchronises the stream).
+   flags[0] != 0 means a traversal exceeded its stack (results invalid). */
+rgx_status rgx_error_flags(rgx_context *ctx, int32_t *flags /*host*/, hipStream_t stream);
+
+const char *rgx_status_string(rgx_status s);
+const char *rgx_last_error(const rgx_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RGX_H */

@@ -1,0 +1,507 @@
+// C ABI of the library (declared in include/rgx.h): argument checking,
+// device-memory ownership of the acceleration structure and the launch
+// descriptors.  All device work is enqueued on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rgx.h"
+#include "common.hpp"
+#include "internal.hpp"
+
+using namespace rgx;
+
+static_assert(RGX_STAT_Q == ST_Q && RGX_STAT_P == ST_P && RGX_STAT_SAMPLES == ST_SAMPLES &&
+                  RGX_STAT_SEGMENTS == ST_SEGMENTS && RGX_STAT_CLOSEST == ST_CLOSEST &&
+                  RGX_STAT_BOX_ONLY == ST_BOX_ONLY && RGX_NSTAT == kNStat,
+              "stat slots");
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct rgx_context {
+  int device = 0;
+  int n_cu = 256;
+  std::string last_error;
+  int32_t *queue = nullptr;        // 8 persistent-launch queues + error flag
+  std::map<std::tuple<int, int, int, int>, int32_t *> tile_orders;
+};
+
+struct rgx_bvh {
+  rgx_context *ctx = nullptr;
+  int64_t n = 0, cap = 0;
+  int32_t sh_degree = 0, sh_k = 1, col_stride = 4, col_cap = 0;
+  float sigma_eps = 0.01f;
+  int morton_bits = 21;
+  int sorted_sel = 0;
+  DevBuf geom_user, aabb_user, aux_user, aux, active, bounds, counters, keys0, keys1, vals0, vals1, hist, geom,
+      aabb, col, nodes, node_box, parent, visit, acc;
+};
+
+static rgx_status fail(rgx_context *ctx, rgx_status s, const std::string &msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
+
+static rgx_status hip_fail(rgx_context *ctx, hipError_t e, const char *where) {
+  return fail(ctx, RGX_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                  \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);  \
+  } while (0)
+
+static hipError_t ensure(DevBuf &b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return hipSuccess;
+  if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+  hipError_t e = hipMalloc(&b.p, std::max<size_t>(bytes, 256));
+  if (e == hipSuccess) b.bytes = std::max<size_t>(bytes, 256);
+  return e;
+}
+
+static void release(DevBuf &b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+extern "C" {
+
+const char *rgx_status_string(rgx_status s) {
+  switch (s) {
+    case RGX_OK: return "ok";
+    case RGX_ERR_INVALID_ARG: return "invalid argument";
+    case RGX_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case RGX_ERR_HIP: return "HIP runtime error";
+    case RGX_ERR_UNSUPPORTED: return "unsupported option";
+    case RGX_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char *rgx_last_error(const rgx_context *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+rgx_status rgx_create(int device, rgx_context **out) {
+  if (!out) return RGX_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return RGX_ERR_INVALID_ARG;
+  rgx_context *ctx = new rgx_context();
+  ctx->device = device;
+  hipError_t e = hipSetDevice(device);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
+  if (e == hipSuccess) {
+    ctx->n_cu = prop.multiProcessorCount;
+    e = hipMalloc((void **)&ctx->queue, 16 * sizeof(int32_t));
+  }
+  if (e == hipSuccess) e = hipMemset(ctx->queue, 0, 16 * sizeof(int32_t));
+  if (e != hipSuccess) {
+    delete ctx;
+    return RGX_ERR_HIP;
+  }
+  *out = ctx;
+  return RGX_OK;
+}
+
+void rgx_destroy(rgx_context *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (auto &kv : ctx->tile_orders) (void)hipFree(kv.second);
+  if (ctx->queue) (void)hipFree(ctx->queue);
+  delete ctx;
+}
+
+void rgx_bvh_destroy(rgx_bvh *b) {
+  if (!b) return;
+  DevBuf *all[] = {&b->geom_user, &b->aabb_user, &b->aux_user, &b->aux, &b->active, &b->bounds, &b->counters, &b->keys0,
+                   &b->keys1, &b->vals0, &b->vals1, &b->hist, &b->geom, &b->aabb, &b->col,
+                   &b->nodes, &b->node_box, &b->parent, &b->visit, &b->acc};
+  for (DevBuf *d : all) release(*d);
+  delete b;
+}
+
+int64_t rgx_bvh_size(const rgx_bvh *b) { return b ? b->n : 0; }
+
+rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_build_opts *opts,
+                         rgx_bvh **bvh, hipStream_t stream) {
+  if (!ctx || !g || !bvh) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  if (g->n <= 0 || g->n > (int64_t)INT32_MAX / 2)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "n out of range");
+  if (g->sh_degree < 0 || g->sh_degree > 3)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "sh_degree must be 0..3");
+  if (!g->means || !g->log_scales || !g->quats || !g->density || !g->sh)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "null parameter array");
+  const float sigma_eps = opts ? opts->sigma_eps : 0.01f;
+  const int bits = (opts && opts->morton_bits) ? opts->morton_bits : 21;
+  if (!(sigma_eps > 0.0f) || !std::isfinite(sigma_eps))
+    return fail(ctx, RGX_ERR_INVALID_ARG, "sigma_eps must be > 0");
+  if (bits < 1 || bits > 21) return fail(ctx, RGX_ERR_INVALID_ARG, "morton_bits must be 1..21");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  rgx_bvh *b = *bvh;
+  const bool fresh = b == nullptr;
+  if (fresh) {
+    b = new rgx_bvh();
+    b->ctx = ctx;
+  }
+  const int64_t n = g->n;
+  const int sh_k = (g->sh_degree + 1) * (g->sh_degree + 1);
+  const int col_stride = (3 * sh_k + 3) & ~3;
+  const int64_t nb = (n + 4095) / 4096;
+  const size_t nodes_n = (size_t)std::max<int64_t>(n - 1, 1);
+  hipError_t e = hipSuccess;
+#define ENS(buf, bytes) \
+  if (e == hipSuccess) e = ensure(b->buf, (bytes))
+  ENS(geom_user, (size_t)n * kGeomFloats * 4);
+  ENS(aabb_user, (size_t)n * 6 * 4);
+  ENS(aux_user, (size_t)n * kAuxFloats * 4);
+  ENS(aux, (size_t)n * kAuxFloats * 4);
+  ENS(active, (size_t)n);
+  ENS(bounds, 64);
+  ENS(counters, 64);
+  ENS(keys0, (size_t)n * 8);
+  ENS(keys1, (size_t)n * 8);
+  ENS(vals0, (size_t)n * 4);
+  ENS(vals1, (size_t)n * 4);
+  ENS(hist, (size_t)nb * 256 * 4);
+  ENS(geom, (size_t)n * kGeomFloats * 4);
+  ENS(aabb, (size_t)n * 6 * 4);
+  ENS(col, (size_t)n * col_stride * 4);
+  ENS(nodes, nodes_n * 16 * 4);
+  ENS(node_box, nodes_n * 6 * 4);
+  ENS(parent, (size_t)(2 * n) * 4);
+  ENS(visit, nodes_n * 4);
+  ENS(acc, (size_t)n * kAccFloats * 4);
+#undef ENS
+  if (e != hipSuccess) {
+    if (fresh) rgx_bvh_destroy(b);
+    return fail(ctx, e == hipErrorOutOfMemory ? RGX_ERR_OUT_OF_MEMORY : RGX_ERR_HIP,
+                std::string("allocation: ") + hipGetErrorString(e));
+  }
+  b->n = n;
+  b->sh_degree = g->sh_degree;
+  b->sh_k = sh_k;
+  b->col_stride = col_stride;
+  b->sigma_eps = sigma_eps;
+  b->morton_bits = bits;
+  BuildArgs a;
+  a.n = n;
+  a.means = g->means; a.log_scales = g->log_scales; a.quats = g->quats; a.density = g->density;
+  a.sh = g->sh;
+  a.sh_k = sh_k; a.col_stride = col_stride; a.morton_bits = bits; a.sigma_eps = sigma_eps;
+  a.geom_user = (float *)b->geom_user.p; a.aabb_user = (float *)b->aabb_user.p;
+  a.aux_user = (float *)b->aux_user.p; a.aux = (float *)b->aux.p;
+  a.active = (uint8_t *)b->active.p; a.bounds = (uint32_t *)b->bounds.p;
+  a.counters = (int32_t *)b->counters.p;
+  a.keys[0] = (uint64_t *)b->keys0.p; a.keys[1] = (uint64_t *)b->keys1.p;
+  a.vals[0] = (uint32_t *)b->vals0.p; a.vals[1] = (uint32_t *)b->vals1.p;
+  a.sort_hist = (uint32_t *)b->hist.p;
+  a.sorted_sel = &b->sorted_sel;
+  a.geom = (float *)b->geom.p; a.aabb = (float *)b->aabb.p; a.col = (float *)b->col.p;
+  a.nodes = (float *)b->nodes.p; a.node_box = (float *)b->node_box.p;
+  a.parent = (int32_t *)b->parent.p; a.visit = (int32_t *)b->visit.p;
+  e = launch_build(a, stream);
+  if (e == hipSuccess) e = launch_fill(b->acc.p, n * kAccFloats, 0u, stream);
+  if (e != hipSuccess) {
+    if (fresh) rgx_bvh_destroy(b);
+    return hip_fail(ctx, e, "build launch");
+  }
+  *bvh = b;
+  return RGX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Launch descriptors
+
+static SceneDev scene_of(const rgx_bvh *b) {
+  SceneDev s;
+  s.geom = (const float *)b->geom.p;
+  s.col = (const float *)b->col.p;
+  s.nodes = (const float *)b->nodes.p;
+  s.aabb = (const float *)b->aabb.p;
+  s.counters = (const int32_t *)b->counters.p;
+  s.perm = (const uint32_t *)(b->sorted_sel ? b->vals1.p : b->vals0.p);
+  s.aux = (const float *)b->aux.p;
+  s.n = b->n;
+  return s;
+}
+
+static int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) r++;
+  return r;
+}
+
+static rgx_status make_opts(rgx_context *ctx, const rgx_bvh *b, const rgx_render_opts *o,
+                            MarchOpts &m) {
+  if (!o) return fail(ctx, RGX_ERR_INVALID_ARG, "null opts");
+  if (!(o->n_s == 1 || o->n_s == 2 || o->n_s == 4 || o->n_s == 8 || o->n_s == 16))
+    return fail(ctx, RGX_ERR_UNSUPPORTED, "n_s must be 1, 2, 4, 8 or 16");
+  if (o->adaptive) {
+    if (!(o->dt_min > 0.0f) || !(o->dt_max >= o->dt_min) || !(o->beta > 0.0f))
+      return fail(ctx, RGX_ERR_INVALID_ARG, "adaptive needs 0 < dt_min <= dt_max and beta > 0");
+  } else if (!(o->dt > 0.0f)) {
+    return fail(ctx, RGX_ERR_INVALID_ARG, "dt must be > 0");
+  }
+  if (!(o->t_eps >= 0.0f)) return fail(ctx, RGX_ERR_INVALID_ARG, "t_eps must be >= 0");
+  if (o->ess < 0 || o->ess > 2) return fail(ctx, RGX_ERR_INVALID_ARG, "ess must be 0, 1 or 2");
+  int tw = o->tile_w, th = o->tile_h;
+  if (tw == 0 && th == 0) { tw = 8; th = 8; }
+  if (o->ray_order == 1 && !(tw * th == 64 && (tw & (tw - 1)) == 0))
+    return fail(ctx, RGX_ERR_INVALID_ARG, "tile_w * tile_h must be 64 with tile_w a power of 2");
+  if (o->ray_order != 0 && o->ray_order != 1)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "ray_order must be 0 or 1");
+  m.adaptive = o->adaptive ? 1 : 0;
+  m.dt = o->dt;
+  m.dt_min = o->dt_min;
+  m.dt_max = o->dt_max;
+  m.inv_beta = o->adaptive ? 1.0f / o->beta : 0.0f;
+  m.n_s = o->n_s;
+  m.t_eps = o->t_eps;
+  m.ess = o->ess;
+  m.brute_force = o->brute_force ? 1 : 0;
+  m.ray_order = o->ray_order;
+  m.tile_w = tw;
+  m.tile_h = th;
+  m.tile_w_log2 = ilog2(tw);
+  m.persistent = o->persistent ? 1 : 0;
+  for (int i = 0; i < 3; i++) m.bg[i] = o->bg[i];
+  m.sh_k = b->sh_k;
+  m.col_stride = b->col_stride;
+  return RGX_OK;
+}
+
+static rgx_status check_camera(rgx_context *ctx, const rgx_camera &c) {
+  if (c.width <= 0 || c.height <= 0 || (int64_t)c.width * c.height > (int64_t)1 << 30)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "camera size out of range");
+  if (c.width > 65535 * 8 || c.height > 65535 * 8)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "camera too large");
+  if (!(c.fx != 0.0f) || !(c.fy != 0.0f)) return fail(ctx, RGX_ERR_INVALID_ARG, "zero focal length");
+  if (!(c.t_near >= 0.0f) || !(c.t_far > c.t_near))
+    return fail(ctx, RGX_ERR_INVALID_ARG, "need 0 <= t_near < t_far");
+  for (int i = 0; i < 12; i++)
+    if (!std::isfinite(c.cam_to_world[i])) return fail(ctx, RGX_ERR_INVALID_ARG, "non-finite pose");
+  return RGX_OK;
+}
+
+static uint32_t interleave2(uint32_t x, uint32_t y) {
+  uint32_t r = 0;
+  for (int b = 0; b < 16; b++) r |= ((x >> b) & 1u) << (2 * b) | ((y >> b) & 1u) << (2 * b + 1);
+  return r;
+}
+
+// Tile coordinates of a view in Morton order of (tx, ty), cached per shape.
+static rgx_status tile_order(rgx_context *ctx, int W, int H, int tw, int th, const int32_t **out) {
+  auto key = std::make_tuple(W, H, tw, th);
+  auto it = ctx->tile_orders.find(key);
+  if (it != ctx->tile_orders.end()) { *out = it->second; return RGX_OK; }
+  const int tx = (W + tw - 1) / tw, ty = (H + th - 1) / th;
+  std::vector<std::pair<uint32_t, int32_t>> v;
+  v.reserve((size_t)tx * ty);
+  for (int y = 0; y < ty; y++)
+    for (int x = 0; x < tx; x++) v.push_back({interleave2(x, y), x | (y << 16)});
+  std::sort(v.begin(), v.end());
+  std::vector<int32_t> codes(v.size());
+  for (size_t i = 0; i < v.size(); i++) codes[i] = v[i].second;
+  int32_t *d = nullptr;
+  HIP_TRY(ctx, hipMalloc(&d, codes.size() * sizeof(int32_t)));
+  HIP_TRY(ctx, hipMemcpy(d, codes.data(), codes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  ctx->tile_orders[key] = d;
+  *out = d;
+  return RGX_OK;
+}
+
+// Split the views into launches of at most kMaxViewsPerLaunch.
+static rgx_status view_tables(rgx_context *ctx, const rgx_camera *cams, int n_views,
+                              const MarchOpts &m, std::vector<ViewTable> &tabs) {
+  if (!cams || n_views <= 0) return fail(ctx, RGX_ERR_INVALID_ARG, "no views");
+  int64_t ray = 0;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPerLaunch) {
+    ViewTable t;
+    memset(&t, 0, sizeof t);
+    int tiles = 0;
+    for (int v = v0; v < std::min(n_views, v0 + kMaxViewsPerLaunch); v++) {
+      const rgx_camera &c = cams[v];
+      rgx_status s = check_camera(ctx, c);
+      if (s != RGX_OK) return s;
+      View &V = t.v[t.n_views++];
+      V.width = c.width;
+      V.height = c.height;
+      if (m.ray_order == 0) {
+        V.tiles_x = (c.width * c.height + 63) / 64;
+        V.tiles_y = 1;
+        V.tile_order = nullptr;
+      } else {
+        V.tiles_x = (c.width + m.tile_w - 1) / m.tile_w;
+        V.tiles_y = (c.height + m.tile_h - 1) / m.tile_h;
+        s = tile_order(ctx, c.width, c.height, m.tile_w, m.tile_h, &V.tile_order);
+        if (s != RGX_OK) return s;
+      }
+      if (!m.adaptive) {
+        // fixed-step sample positions come from exact integer-to-float products
+        const double segs = ((double)c.t_far - (double)c.t_near) / ((double)m.dt * m.n_s);
+        if (segs > (double)(1 << 22))
+          return fail(ctx, RGX_ERR_INVALID_ARG, "(t_far - t_near) / (dt * n_s) exceeds 2^22");
+      }
+      V.tile_begin = tiles;
+      if (ray > INT32_MAX - (int64_t)c.width * c.height)
+        return fail(ctx, RGX_ERR_INVALID_ARG, "too many rays in one call");
+      V.ray_begin = (int32_t)ray;
+      tiles += V.tiles_x * V.tiles_y;
+      ray += (int64_t)c.width * c.height;
+      V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
+      memcpy(V.c2w, c.cam_to_world, sizeof V.c2w);
+      V.t_near = c.t_near;
+      V.t_far = c.t_far;
+    }
+    t.n_tiles = tiles;
+    tabs.push_back(t);
+  }
+  return RGX_OK;
+}
+
+static LaunchShape shape_for(rgx_context *ctx, const MarchOpts &m, int n_tiles) {
+  LaunchShape ls;
+  ls.queue = ctx->queue;
+  ls.error_flag = ctx->queue + 8;
+  const int nb = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  ls.grid = m.persistent ? std::min(nb, ctx->n_cu * 8) : nb;
+  if (ls.grid < 1) ls.grid = 1;
+  return ls;
+}
+
+extern "C" {
+
+rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
+                              int32_t n_views, const rgx_render_opts *opts, float *out_rgb,
+                              float *out_T, int32_t *stats, hipStream_t stream) {
+  if (!ctx || !bvh || !out_rgb || !out_T) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  MarchOpts m;
+  rgx_status s = make_opts(ctx, bvh, opts, m);
+  if (s != RGX_OK) return s;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  std::vector<ViewTable> tabs;
+  if ((s = view_tables(ctx, cams, n_views, m, tabs)) != RGX_OK) return s;
+  const SceneDev sd = scene_of(bvh);
+  FwdOut out;
+  memset(&out, 0, sizeof out);
+  out.rgb = out_rgb;
+  out.T = out_T;
+  out.stats = stats;
+  for (const ViewTable &t : tabs) {
+    if (t.n_tiles == 0) continue;
+    HIP_TRY(ctx, launch_forward(sd, t, m, out, shape_for(ctx, m, t.n_tiles), stream));
+  }
+  return RGX_OK;
+}
+
+rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
+                               int32_t n_views, const rgx_render_opts *opts, const float *out_rgb,
+                               const float *out_T, const float *grad_rgb, const float *grad_T,
+                               const rgx_grads *grads, hipStream_t stream) {
+  if (!ctx || !bvh || !out_rgb || !out_T || !grad_rgb || !grads)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  if (!grads->means || !grads->log_scales || !grads->quats || !grads->density || !grads->sh)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "null gradient buffer");
+  MarchOpts m;
+  rgx_status s = make_opts(ctx, bvh, opts, m);
+  if (s != RGX_OK) return s;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  std::vector<ViewTable> tabs;
+  if ((s = view_tables(ctx, cams, n_views, m, tabs)) != RGX_OK) return s;
+  const SceneDev sd = scene_of(bvh);
+  // the accumulators are zero: cleared by the build and by every finalisation
+  BwdIn in;
+  in.rgb = out_rgb;
+  in.T = out_T;
+  in.grad_rgb = grad_rgb;
+  in.grad_T = grad_T;
+  in.acc = (float *)bvh->acc.p;
+  for (const ViewTable &t : tabs) {
+    if (t.n_tiles == 0) continue;
+    HIP_TRY(ctx, launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles), stream));
+  }
+  HIP_TRY(ctx, launch_finalize_grads(sd, bvh->sh_k, (float *)bvh->acc.p, grads->means, grads->log_scales, grads->quats,
+                                     grads->density, grads->sh, grads->accumulate, stream));
+  return RGX_OK;
+}
+
+rgx_status rgx_dump_hits(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cam,
+                         const rgx_render_opts *opts, const int32_t *pix, int32_t n_rays,
+                         int32_t cap, float *seg_a, int32_t *ids, int32_t *count,
+                         hipStream_t stream) {
+  if (!ctx || !bvh || !cam || !pix || !seg_a || !ids || !count || n_rays <= 0 || cap <= 0)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "bad argument");
+  MarchOpts m;
+  rgx_status s = make_opts(ctx, bvh, opts, m);
+  if (s != RGX_OK) return s;
+  m.persistent = 0;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((s = check_camera(ctx, *cam)) != RGX_OK) return s;
+  ViewTable t;
+  memset(&t, 0, sizeof t);
+  t.n_views = 1;
+  View &V = t.v[0];
+  V.width = cam->width; V.height = cam->height;
+  V.fx = cam->fx; V.fy = cam->fy; V.cx = cam->cx; V.cy = cam->cy;
+  memcpy(V.c2w, cam->cam_to_world, sizeof V.c2w);
+  V.t_near = cam->t_near; V.t_far = cam->t_far;
+  t.n_tiles = (n_rays + 63) / 64;
+  FwdOut out;
+  memset(&out, 0, sizeof out);
+  out.dump_pix = pix;
+  out.dump_n = n_rays;
+  out.dump_cap = cap;
+  out.dump_a = seg_a;
+  out.dump_ids = ids;
+  out.dump_count = count;
+  HIP_TRY(ctx, launch_forward(scene_of(bvh), t, m, out, shape_for(ctx, m, t.n_tiles), stream));
+  return RGX_OK;
+}
+
+rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *b, uint64_t *keys, int32_t *perm,
+                         float *aabb, float *nodes, int64_t *n_active, hipStream_t stream) {
+  if (!ctx || !b) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  const size_t n = (size_t)b->n;
+  if (keys)
+    HIP_TRY(ctx, hipMemcpy(keys, b->sorted_sel ? b->keys1.p : b->keys0.p, n * 8, hipMemcpyDeviceToHost));
+  if (perm)
+    HIP_TRY(ctx, hipMemcpy(perm, b->sorted_sel ? b->vals1.p : b->vals0.p, n * 4, hipMemcpyDeviceToHost));
+  if (aabb) HIP_TRY(ctx, hipMemcpy(aabb, b->aabb.p, n * 24, hipMemcpyDeviceToHost));
+  if (nodes)
+    HIP_TRY(ctx, hipMemcpy(nodes, b->nodes.p, std::max<size_t>(n - 1, 1) * 64, hipMemcpyDeviceToHost));
+  if (n_active) {
+    int32_t c = 0;
+    HIP_TRY(ctx, hipMemcpy(&c, b->counters.p, 4, hipMemcpyDeviceToHost));
+    *n_active = c;
+  }
+  return RGX_OK;
+}
+
+rgx_status rgx_error_flags(rgx_context *ctx, int32_t *flags, hipStream_t stream) {
+  if (!ctx || !flags) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  HIP_TRY(ctx, hipMemcpy(flags, ctx->queue + 8, 4, hipMemcpyDeviceToHost));
+  return RGX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,413 @@
+// Acceleration-structure build: per-Gaussian preprocessing, Z-order (Morton)
+// keys, a stable LSD radix sort, the Z-ordered pack, and a Karras LBVH with a
+// bottom-up refit.  Every size follows from N on the host; the number of
+// active Gaussians stays on the device, so the whole build is asynchronous.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace rgx {
+
+// ---------------------------------------------------------------------------
+// Order-preserving float <-> uint32 map for atomic min/max of floats.
+__device__ __forceinline__ uint32_t f2ord(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__global__ void k_build_init(uint32_t *bounds, int32_t *counters) {
+  int t = threadIdx.x;
+  if (t < 3) bounds[t] = 0xffffffffu;        // min
+  else if (t < 6) bounds[t] = 0u;            // max
+  if (t < 8) counters[t] = 0;
+}
+
+// Per Gaussian (user order): Sec. 3.1 Eq. 1 and the sigma_eps level-set
+// ellipsoid of Supp. B.  Writes the geometry record, the padded AABB and an
+// active flag; accumulates the bounds of the active means.
+__global__ __launch_bounds__(256) void k_preprocess(int64_t n, const float *__restrict__ means,
+                                                    const float *__restrict__ log_scales,
+                                                    const float *__restrict__ quats,
+                                                    const float *__restrict__ density,
+                                                    float sigma_eps, float *__restrict__ geom,
+                                                    float *__restrict__ aabb,
+                                                    float *__restrict__ aux,
+                                                    uint8_t *__restrict__ active,
+                                                    uint32_t *__restrict__ bounds,
+                                                    int32_t *__restrict__ counters) {
+  __shared__ uint32_t sb[6];
+  __shared__ int32_t scount;
+  if (threadIdx.x < 3) sb[threadIdx.x] = 0xffffffffu;
+  else if (threadIdx.x < 6) sb[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) scount = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float mu[3], ls[3], q[4];
+    for (int k = 0; k < 3; k++) { mu[k] = means[3 * i + k]; ls[k] = log_scales[3 * i + k]; }
+    for (int k = 0; k < 4; k++) q[k] = quats[4 * i + k];
+    const float sig = density[i];
+    const float qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    bool ok = isfinite(mu[0]) && isfinite(mu[1]) && isfinite(mu[2]) && isfinite(ls[0]) &&
+              isfinite(ls[1]) && isfinite(ls[2]) && isfinite(qn2) && qn2 > 0.0f &&
+              isfinite(sig) && sig > sigma_eps;
+    float s[3];
+    for (int k = 0; k < 3; k++) { s[k] = expf(ls[k]); ok = ok && s[k] > 0.0f && isfinite(s[k]); }
+    float g[kGeomFloats];
+    for (int k = 0; k < kGeomFloats; k++) g[k] = 0.0f;
+    float lo[3] = {1.0f, 1.0f, 1.0f}, hi[3] = {-1.0f, -1.0f, -1.0f};
+    float ax[kAuxFloats] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (ok) {
+      const float rn = rsqrtf(qn2);
+      ax[0] = s[0]; ax[1] = s[1]; ax[2] = s[2];
+      ax[7] = sqrtf(qn2);
+      ax[3] = q[0] / ax[7]; ax[4] = q[1] / ax[7]; ax[5] = q[2] / ax[7]; ax[6] = q[3] / ax[7];
+      const float w = q[0] * rn, x = q[1] * rn, y = q[2] * rn, z = q[3] * rn;
+      float R[9];
+      R[0] = 1.0f - 2.0f * (y * y + z * z); R[1] = 2.0f * (x * y - w * z); R[2] = 2.0f * (x * z + w * y);
+      R[3] = 2.0f * (x * y + w * z); R[4] = 1.0f - 2.0f * (x * x + z * z); R[5] = 2.0f * (y * z - w * x);
+      R[6] = 2.0f * (x * z - w * y); R[7] = 2.0f * (y * z + w * x); R[8] = 1.0f - 2.0f * (x * x + y * y);
+      const float k2 = 2.0f * logf(sig / sigma_eps);
+      const float k = sqrtf(k2);
+      for (int r = 0; r < 3; r++) {
+        g[G_MU + r] = mu[r];
+        // row r of M = S^-1 R^T is column r of R divided by s_r
+        for (int c = 0; c < 3; c++) g[G_M + 3 * r + c] = R[3 * c + r] / s[r];
+      }
+      g[G_K2] = k2;
+      g[G_SIG] = sig;
+      g[G_L2SIG] = log2f(sig);
+      // minimal AABB half-lengths L_i = k sqrt(sum_j r_ij^2 s_j^2) (Supp. B), padded
+      // outward so that every point of an FP32 ray/ellipsoid interval lies inside
+      float amax = fmaxf(fabsf(mu[0]), fmaxf(fabsf(mu[1]), fabsf(mu[2])));
+      for (int r = 0; r < 3; r++) {
+        float acc = 0.0f;
+        for (int c = 0; c < 3; c++) acc += R[3 * r + c] * R[3 * r + c] * s[c] * s[c];
+        float L = k * sqrtf(acc);
+        L = L * 1.0001f + 2e-6f * (amax + L) + 1e-30f;
+        lo[r] = mu[r] - L;
+        hi[r] = mu[r] + L;
+      }
+      atomicMin(&sb[0], f2ord(mu[0])); atomicMin(&sb[1], f2ord(mu[1])); atomicMin(&sb[2], f2ord(mu[2]));
+      atomicMax(&sb[3], f2ord(mu[0])); atomicMax(&sb[4], f2ord(mu[1])); atomicMax(&sb[5], f2ord(mu[2]));
+      atomicAdd(&scount, 1);
+    }
+    float4 *gp = reinterpret_cast<float4 *>(geom + (size_t)kGeomFloats * i);
+    for (int k = 0; k < 4; k++) gp[k] = make_float4(g[4 * k], g[4 * k + 1], g[4 * k + 2], g[4 * k + 3]);
+    for (int k = 0; k < 3; k++) { aabb[6 * i + k] = lo[k]; aabb[6 * i + 3 + k] = hi[k]; }
+    for (int k = 0; k < kAuxFloats; k++) aux[kAuxFloats * i + k] = ax[k];
+    active[i] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) atomicMin(&bounds[threadIdx.x], sb[threadIdx.x]);
+  else if (threadIdx.x < 6) atomicMax(&bounds[threadIdx.x], sb[threadIdx.x]);
+  if (threadIdx.x == 0 && scount) atomicAdd(&counters[0], scount);
+}
+
+// Spread the low 21 bits of v so that bit b lands at bit 3b.
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+// Z-order index of the normalised, quantised mean (Sec. 3.3).  Inactive
+// Gaussians get the key 2^(3*bits), above every active key.
+__global__ __launch_bounds__(256) void k_morton(int64_t n, const float *__restrict__ means,
+                                                const uint8_t *__restrict__ active,
+                                                const uint32_t *__restrict__ bounds, int bits,
+                                                uint64_t *__restrict__ keys,
+                                                uint32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t key = 1ull << (3 * bits);
+  if (active[i]) {
+    const float qmax = (float)((1u << bits) - 1u);
+    uint64_t c[3];
+    for (int k = 0; k < 3; k++) {
+      const float lo = ord2f(bounds[k]), hi = ord2f(bounds[3 + k]);
+      const float ext = hi - lo;
+      float u = ext > 0.0f ? (means[3 * i + k] - lo) / ext : 0.0f;
+      u = fminf(fmaxf(u, 0.0f), 1.0f);
+      c[k] = (uint64_t)(u * qmax + 0.5f);
+      if (c[k] > (uint64_t)qmax) c[k] = (uint64_t)qmax;
+    }
+    key = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
+  }
+  keys[i] = key;
+  vals[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits.  Each block owns a tile of
+// kSortItems keys; a pass is histogram -> global exclusive scan (digit-major)
+// -> stable scatter with per-wave ballot multisplit.
+
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortItems = kSortThreads * kSortRounds;
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ keys,
+                                                             int64_t n, int shift,
+                                                             uint32_t *__restrict__ hist,
+                                                             int nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortItems;
+  for (int r = 0; r < kSortRounds; r++) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xff], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `count` uint32 in place; a single block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t *__restrict__ data, int64_t count) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t base = 0; base < count; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    uint32_t v = i < count ? data[i] : 0u;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+      uint32_t s = lane < 16 ? wsum[lane] : 0u;
+      for (int o = 1; o < 16; o <<= 1) {
+        uint32_t y = __shfl_up(s, o, 64);
+        if (lane >= o) s += y;
+      }
+      if (lane < 16) wsum[lane] = s;
+    }
+    __syncthreads();
+    const uint32_t before = carry + (wid ? wsum[wid - 1] : 0u) + x - v;
+    if (i < count) data[i] = before;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = before + v;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint64_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+    uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, int64_t n, int shift,
+    const uint32_t *__restrict__ hist, int nblocks) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcount[kWavesPerBlock][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  base[threadIdx.x] = hist[(size_t)threadIdx.x * nblocks + blockIdx.x];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t tile = (int64_t)blockIdx.x * kSortItems;
+  for (int r = 0; r < kSortRounds; r++) {
+    for (int w = 0; w < kWavesPerBlock; w++) wcount[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = tile + r * kSortThreads + threadIdx.x;
+    const bool valid = i < n;
+    uint64_t key = 0;
+    uint32_t val = 0;
+    uint32_t digit = 0;
+    if (valid) { key = keys_in[i]; val = vals_in[i]; digit = (uint32_t)(key >> shift) & 0xffu; }
+    // lanes of this wave holding the same digit
+    uint64_t same = ballot(valid);
+    for (int b = 0; b < 8; b++) {
+      const uint64_t bal = ballot(((digit >> b) & 1u) != 0);
+      same &= ((digit >> b) & 1u) ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(same & lt_mask);
+    if (valid && rank == 0) wcount[wid][digit] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = base[digit] + rank;
+      for (int w = 0; w < wid; w++) off += wcount[w][digit];
+      keys_out[off] = key;
+      vals_out[off] = val;
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    for (int w = 0; w < kWavesPerBlock; w++) tot += wcount[w][threadIdx.x];
+    base[threadIdx.x] += tot;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Z-ordered pack of the geometry, colour and AABB records of active Gaussians.
+__global__ __launch_bounds__(256) void k_pack(int64_t n, const int32_t *__restrict__ counters,
+                                              const uint32_t *__restrict__ perm,
+                                              const float *__restrict__ geom_user,
+                                              const float *__restrict__ aabb_user,
+                                              const float *__restrict__ aux_user,
+                                              const float *__restrict__ sh_user, int sh_k,
+                                              int col_stride, float *__restrict__ geom,
+                                              float *__restrict__ aabb, float *__restrict__ aux,
+                                              float *__restrict__ col) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_active = counters[0];
+  if (i >= n_active) return;
+  const int64_t src = perm[i];
+  const float4 *gs = reinterpret_cast<const float4 *>(geom_user + (size_t)kGeomFloats * src);
+  float4 *gd = reinterpret_cast<float4 *>(geom + (size_t)kGeomFloats * i);
+  for (int k = 0; k < 4; k++) gd[k] = gs[k];
+  for (int k = 0; k < 6; k++) aabb[6 * i + k] = aabb_user[6 * src + k];
+  for (int k = 0; k < kAuxFloats; k++) aux[kAuxFloats * i + k] = aux_user[kAuxFloats * src + k];
+  const float *cs = sh_user + (size_t)3 * sh_k * src;
+  float *cd = col + (size_t)col_stride * i;
+  for (int k = 0; k < 3 * sh_k; k++) cd[k] = cs[k];
+  for (int k = 3 * sh_k; k < col_stride; k++) cd[k] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Karras LBVH over the sorted keys of the active Gaussians.  Internal node i
+// covers a key range with i at one end; duplicate keys are split by index.
+__device__ __forceinline__ int lcp(const uint64_t *__restrict__ k, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  const uint64_t a = k[i], b = k[j];
+  if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+  return __clzll(a ^ b);
+}
+
+__global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
+                                                        const int32_t *__restrict__ counters,
+                                                        const uint64_t *__restrict__ keys,
+                                                        const float *__restrict__ aabb,
+                                                        float4 *__restrict__ nodes,
+                                                        int32_t *__restrict__ parent,
+                                                        int32_t *__restrict__ visit) {
+  const int n = counters[0];
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= n_max) return;
+  const int i = (int)tid;
+  // parent[0 .. n-2] internal nodes, parent[n-1 .. 2n-2] leaves
+  if (n == 1 && i == 0) {
+    nodes[0] = make_float4(aabb[0], aabb[1], aabb[2], __int_as_float(~0));
+    nodes[1] = make_float4(aabb[3], aabb[4], aabb[5], __int_as_float(kNoChild));
+    nodes[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    nodes[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  if (i >= n - 1) return;
+  visit[i] = 0;
+  if (i == 0) parent[0] = -1;
+  const int d = (lcp(keys, n, i, i + 1) - lcp(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+  const int dmin = lcp(keys, n, i, i - d);
+  int64_t lmax = 2;
+  while (lmax < 2 * (int64_t)n && lcp(keys, n, i, (int)(i + lmax * d)) > dmin) lmax <<= 1;
+  int l = 0;
+  for (int64_t t = lmax >> 1; t >= 1; t >>= 1) {
+    const int64_t jj = i + (l + t) * d;
+    if (jj >= 0 && jj < n && lcp(keys, n, i, (int)jj) > dmin) l += (int)t;
+  }
+  const int j = i + l * d;
+  const int dnode = lcp(keys, n, i, j);
+  int s = 0;
+  int t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (lcp(keys, n, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  const int gamma = i + s * d + (d < 0 ? -1 : 0);
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  const int left = (lo == gamma) ? ~gamma : gamma;
+  const int right = (hi == gamma + 1) ? ~(gamma + 1) : gamma + 1;
+  if (left < 0) parent[(n - 1) + gamma] = i; else parent[left] = i;
+  if (right < 0) parent[(n - 1) + gamma + 1] = i; else parent[right] = i;
+  float4 *nd = nodes + 4 * (size_t)i;
+  nd[0].w = __int_as_float(left);
+  nd[1].w = __int_as_float(right);
+}
+
+// Bottom-up refit: the second thread to reach a node writes both child boxes
+// into it and its union into node_box, then continues upward.
+__device__ __forceinline__ float load_relaxed(const float *p) {
+  return __int_as_float(__hip_atomic_load(reinterpret_cast<const int *>(p), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__global__ __launch_bounds__(256) void k_lbvh_refit(int64_t n_max, const int32_t *__restrict__ counters,
+                                                    const float *__restrict__ aabb,
+                                                    float4 *__restrict__ nodes,
+                                                    const int32_t *__restrict__ parent,
+                                                    int32_t *__restrict__ visit,
+                                                    float *__restrict__ node_box) {
+  const int n = counters[0];
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < 2 || tid >= n) return;
+  int node = parent[(n - 1) + (int)tid];
+  for (int depth = 0; node >= 0 && node < n - 1 && depth < 256; depth++) {
+    __threadfence();
+    if (atomicAdd(&visit[node], 1) == 0) return;   // the sibling is still on its way
+    __threadfence();
+    float4 *nd = nodes + 4 * (size_t)node;
+    const int ch[2] = {__float_as_int(nd[0].w), __float_as_int(nd[1].w)};
+    float b[2][6];
+    for (int c = 0; c < 2; c++) {
+      const float *src = ch[c] < 0 ? aabb + 6 * (size_t)(~ch[c]) : node_box + 6 * (size_t)ch[c];
+      for (int k = 0; k < 6; k++) b[c][k] = load_relaxed(src + k);
+    }
+    nd[0] = make_float4(b[0][0], b[0][1], b[0][2], __int_as_float(ch[0]));
+    nd[1] = make_float4(b[0][3], b[0][4], b[0][5], __int_as_float(ch[1]));
+    nd[2] = make_float4(b[1][0], b[1][1], b[1][2], 0.0f);
+    nd[3] = make_float4(b[1][3], b[1][4], b[1][5], 0.0f);
+    float* ob = node_box + 6 * (size_t)node;
+    for (int k = 0; k < 3; k++) {
+      __hip_atomic_store(reinterpret_cast<int *>(ob + k), __float_as_int(fminf(b[0][k], b[1][k])),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(reinterpret_cast<int *>(ob + 3 + k),
+                         __float_as_int(fmaxf(b[0][3 + k], b[1][3 + k])), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    node = parent[node];
+  }
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
+  const int64_t n = a.n;
+  k_build_init<<<1, 64, 0, st>>>(a.bounds, a.counters);
+  k_preprocess<<<nblk(n, 256), 256, 0, st>>>(n, a.means, a.log_scales, a.quats, a.density,
+                                             a.sigma_eps, a.geom_user, a.aabb_user, a.aux_user, a.active,
+                                             a.bounds, a.counters);
+  k_morton<<<nblk(n, 256), 256, 0, st>>>(n, a.means, a.active, a.bounds, a.morton_bits,
+                                         a.keys[0], a.vals[0]);
+  const int nb = (int)nblk(n, kSortItems);
+  const int passes = (3 * a.morton_bits + 1 + 7) / 8;
+  int cur = 0;
+  for (int p = 0; p < passes; p++) {
+    const int shift = 8 * p;
+    k_radix_hist<<<nb, kSortThreads, 0, st>>>(a.keys[cur], n, shift, a.sort_hist, nb);
+    k_scan_exclusive<<<1, 1024, 0, st>>>(a.sort_hist, (int64_t)256 * nb);
+    k_radix_scatter<<<nb, kSortThreads, 0, st>>>(a.keys[cur], a.vals[cur], a.keys[cur ^ 1],
+                                                 a.vals[cur ^ 1], n, shift, a.sort_hist, nb);
+    cur ^= 1;
+  }
+  *a.sorted_sel = cur;
+  k_pack<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.vals[cur], a.geom_user, a.aabb_user,
+                                       a.aux_user, a.sh, a.sh_k, a.col_stride, a.geom, a.aabb,
+                                       a.aux, a.col);
+  k_lbvh_hierarchy<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.keys[cur], a.aabb,
+                                                 reinterpret_cast<float4 *>(a.nodes), a.parent,
+                                                 a.visit);
+  k_lbvh_refit<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.aabb,
+                                             reinterpret_cast<float4 *>(a.nodes), a.parent,
+                                             a.visit, a.node_box);
+  return hipGetLastError();
+}
+
+}  // namespace rgx

@@ -1,0 +1,72 @@
+// Host-side launch interfaces between the C ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace rgx {
+
+struct BuildArgs {
+  int64_t n;
+  const float *means, *log_scales, *quats, *density, *sh;
+  int sh_k, col_stride, morton_bits;
+  float sigma_eps;
+  // scratch (user order)
+  float *geom_user, *aabb_user, *aux_user;
+  uint8_t *active;
+  uint32_t *bounds;          // 6 ordered floats
+  int32_t *counters;         // [0] active count
+  uint64_t *keys[2];
+  uint32_t *vals[2];
+  uint32_t *sort_hist;
+  int *sorted_sel;           // (host) which ping-pong buffer holds the result
+  // outputs (Z order)
+  float *geom, *aabb, *col, *aux, *nodes, *node_box;
+  int32_t *parent, *visit;
+};
+hipError_t launch_build(const BuildArgs &a, hipStream_t st);
+
+struct SceneDev {
+  const float *geom;          // [n,16]
+  const float *col;           // [n,col_stride]
+  const float *nodes;         // [max(n-1,1),16]
+  const float *aabb;          // [n,6]
+  const int32_t *counters;    // [0] = active count
+  const uint32_t *perm;       // Z index -> user index
+  const float *aux;           // [n,8] s.xyz, unit quaternion wxyz, |q| (Z order)
+  int64_t n;
+};
+
+struct FwdOut {
+  float *rgb, *T;
+  int32_t *stats;            // nullable
+  // hit dump (debug)
+  const int32_t *dump_pix;
+  int32_t dump_n, dump_cap;
+  float *dump_a;
+  int32_t *dump_ids, *dump_count;
+};
+
+struct BwdIn {
+  const float *rgb, *T, *grad_rgb, *grad_T;
+  float *acc;                // [n, 64] packed-order gradient accumulators
+};
+
+struct LaunchShape {
+  int grid;
+  int32_t *queue;            // persistent tile queues (8 counters), zeroed by the launch
+  int32_t *error_flag;
+};
+
+hipError_t launch_forward(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
+                          const FwdOut &out, const LaunchShape &ls, hipStream_t st);
+hipError_t launch_backward(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
+                           const BwdIn &in, const LaunchShape &ls, hipStream_t st);
+hipError_t launch_finalize_grads(const SceneDev &s, int sh_k, float *acc, float *g_means,
+                                 float *g_log_scales, float *g_quats, float *g_density,
+                                 float *g_sh, int accumulate, hipStream_t st);
+hipError_t launch_fill(void *p, int64_t n_words, uint32_t value, hipStream_t st);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+
+}  // namespace rgx

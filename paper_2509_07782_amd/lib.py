@@ -1,0 +1,238 @@
+"""ctypes binding of the C ABI in include/rgx.h (argument marshalling only).
+
+Every step of the path runs in librgx.so; this module converts Python
+objects into the C structures and passes device pointers (torch tensors'
+data_ptr) and the current HIP stream.  It raises if the library is missing:
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librgx.so")
+
+RGX_OK = 0
+NSTAT = 8
+STAT_NAMES = ("Q", "P", "samples", "segments", "closest", "box_only")
+
+
+class RgxError(RuntimeError):
+    pass
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("means", C.c_void_p),
+                ("log_scales", C.c_void_p), ("quats", C.c_void_p), ("density", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("sigma_eps", C.c_float), ("morton_bits", C.c_int32)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("cam_to_world", C.c_float * 12),
+                ("t_near", C.c_float), ("t_far", C.c_float)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("adaptive", C.c_int32), ("dt", C.c_float), ("dt_min", C.c_float),
+                ("dt_max", C.c_float), ("beta", C.c_float), ("n_s", C.c_int32),
+                ("t_eps", C.c_float), ("ess", C.c_int32), ("brute_force", C.c_int32),
+                ("ray_order", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+                ("persistent", C.c_int32), ("bg", C.c_float * 3)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("density", C.c_void_p), ("sh", C.c_void_p), ("accumulate", C.c_int32)]
+
+
+EXPORTS = ("rgx_create", "rgx_destroy", "rgx_build_bvh", "rgx_bvh_destroy", "rgx_bvh_size",
+           "rgx_render_forward", "rgx_render_backward", "rgx_dump_hits", "rgx_bvh_debug",
+           "rgx_error_flags", "rgx_status_string", "rgx_last_error")
+
+_LIB = None
+
+
+def load():
+    """Load librgx.so (built in-tree by build.py); raises if it is absent."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RgxError(f"{LIB_PATH} is missing: build it with paper_2509_07782_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, st = C.c_void_p, C.c_int
+    L.rgx_create.argtypes = [C.c_int, C.POINTER(vp)]
+    L.rgx_create.restype = st
+    L.rgx_destroy.argtypes = [vp]
+    L.rgx_destroy.restype = None
+    L.rgx_build_bvh.argtypes = [vp, C.POINTER(Gaussians), C.POINTER(BuildOpts), C.POINTER(vp), vp]
+    L.rgx_build_bvh.restype = st
+    L.rgx_bvh_destroy.argtypes = [vp]
+    L.rgx_bvh_destroy.restype = None
+    L.rgx_bvh_size.argtypes = [vp]
+    L.rgx_bvh_size.restype = C.c_int64
+    L.rgx_render_forward.argtypes = [vp, vp, C.POINTER(Camera), C.c_int32, C.POINTER(RenderOpts),
+                                     vp, vp, vp, vp]
+    L.rgx_render_forward.restype = st
+    L.rgx_render_backward.argtypes = [vp, vp, C.POINTER(Camera), C.c_int32,
+                                      C.POINTER(RenderOpts), vp, vp, vp, vp, C.POINTER(Grads), vp]
+    L.rgx_render_backward.restype = st
+    L.rgx_dump_hits.argtypes = [vp, vp, C.POINTER(Camera), C.POINTER(RenderOpts), vp, C.c_int32,
+                                C.c_int32, vp, vp, vp, vp]
+    L.rgx_dump_hits.restype = st
+    L.rgx_bvh_debug.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]
+    L.rgx_bvh_debug.restype = st
+    L.rgx_error_flags.argtypes = [vp, C.POINTER(C.c_int32), vp]
+    L.rgx_error_flags.restype = st
+    L.rgx_status_string.argtypes = [st]
+    L.rgx_status_string.restype = C.c_char_p
+    L.rgx_last_error.argtypes = [vp]
+    L.rgx_last_error.restype = C.c_char_p
+    _LIB = L
+    return L
+
+
+def check(rc, ctx=None, what=""):
+    if rc != RGX_OK:
+        L = load()
+        msg = L.rgx_status_string(rc).decode()
+        detail = L.rgx_last_error(ctx).decode() if ctx else ""
+        raise RgxError(f"{what}: {msg} ({rc}) {detail}")
+
+
+def make_camera(cam) -> Camera:
+    c = Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    flat = [float(v) for v in __import__("numpy").asarray(cam.cam_to_world, "float32").reshape(12)]
+    for i in range(12):
+        c.cam_to_world[i] = flat[i]
+    c.t_near, c.t_far = float(cam.t_near), float(cam.t_far)
+    return c
+
+
+def camera_array(cams):
+    arr = (Camera * len(cams))()
+    for i, cam in enumerate(cams):
+        arr[i] = make_camera(cam)
+    return arr
+
+
+def make_opts(o) -> RenderOpts:
+    r = RenderOpts()
+    r.adaptive = int(bool(o.adaptive))
+    r.dt, r.dt_min, r.dt_max, r.beta = o.dt, o.dt_min, o.dt_max, o.beta
+    r.n_s, r.t_eps, r.ess = int(o.n_s), float(o.t_eps), int(o.ess)
+    r.brute_force = int(bool(o.brute_force))
+    r.ray_order = int(o.ray_order)
+    r.tile_w, r.tile_h = int(o.tile_w), int(o.tile_h)
+    r.persistent = int(bool(o.persistent))
+    for i in range(3):
+        r.bg[i] = float(o.bg[i])
+    return r
+
+
+class Context:
+    """Owns an rgx_context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        L = load()
+        h = C.c_void_p()
+        check(L.rgx_create(int(device), C.byref(h)), None, "rgx_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().rgx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error_flags(self, stream=0) -> int:
+        f = C.c_int32(0)
+        check(load().rgx_error_flags(self.h, C.byref(f), C.c_void_p(stream)), self.h, "error_flags")
+        return int(f.value)
+
+
+class BVH:
+    """Owns an rgx_bvh; rebuilt in place by build()."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.h = C.c_void_p()
+
+    def build(self, means, log_scales, quats, density, sh, sh_degree, sigma_eps=0.01,
+              morton_bits=21, stream=0):
+        g = Gaussians(int(means.shape[0]), int(sh_degree), means.data_ptr(),
+                      log_scales.data_ptr(), quats.data_ptr(), density.data_ptr(), sh.data_ptr())
+        o = BuildOpts(float(sigma_eps), int(morton_bits))
+        check(load().rgx_build_bvh(self.ctx.h, C.byref(g), C.byref(o), C.byref(self.h),
+                                   C.c_void_p(stream)), self.ctx.h, "rgx_build_bvh")
+        self.n = int(means.shape[0])
+        self.sh_degree = int(sh_degree)
+        return self
+
+    def close(self):
+        if self.h:
+            load().rgx_bvh_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def debug(self, stream=0):
+        """Host copies of keys, perm, leaf AABBs, nodes and the active count."""
+        import numpy as np
+        n = self.n
+        keys = np.zeros(n, np.uint64)
+        perm = np.zeros(n, np.int32)
+        aabb = np.zeros((n, 6), np.float32)
+        nodes = np.zeros((max(n - 1, 1), 16), np.float32)
+        na = C.c_int64(0)
+        check(load().rgx_bvh_debug(self.ctx.h, self.h, keys.ctypes.data, perm.ctypes.data,
+                                   aabb.ctypes.data, nodes.ctypes.data, C.byref(na),
+                                   C.c_void_p(stream)), self.ctx.h, "rgx_bvh_debug")
+        return keys, perm, aabb, nodes, int(na.value)
+
+
+def render_forward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, stats=None, stream=0):
+    arr = camera_array(cams)
+    o = make_opts(opts)
+    check(load().rgx_render_forward(ctx.h, bvh.h, arr, len(cams), C.byref(o), out_rgb.data_ptr(),
+                                    out_T.data_ptr(), None if stats is None else stats.data_ptr(),
+                                    C.c_void_p(stream)), ctx.h, "rgx_render_forward")
+
+
+def render_backward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, grad_rgb, grad_T, grads,
+                    accumulate=False, stream=0):
+    arr = camera_array(cams)
+    o = make_opts(opts)
+    g = Grads(grads["means"].data_ptr(), grads["log_scales"].data_ptr(),
+              grads["quats"].data_ptr(), grads["density"].data_ptr(), grads["sh"].data_ptr(),
+              int(bool(accumulate)))
+    check(load().rgx_render_backward(ctx.h, bvh.h, arr, len(cams), C.byref(o), out_rgb.data_ptr(),
+                                     out_T.data_ptr(), grad_rgb.data_ptr(),
+                                     None if grad_T is None else grad_T.data_ptr(), C.byref(g),
+                                     C.c_void_p(stream)), ctx.h, "rgx_render_backward")
+
+
+def dump_hits(ctx: Context, bvh: BVH, cam, opts, pix, cap, seg_a, ids, count, stream=0):
+    c = make_camera(cam)
+    o = make_opts(opts)
+    check(load().rgx_dump_hits(ctx.h, bvh.h, C.byref(c), C.byref(o), pix.data_ptr(),
+                               int(pix.numel()), int(cap), seg_a.data_ptr(), ids.data_ptr(),
+                               count.data_ptr(), C.c_void_p(stream)), ctx.h, "rgx_dump_hits")

@@ -1,0 +1,199 @@
+"""GPU forward path through the C ABI against the FP64 oracle, plus the
+self-consistency invariants of the method (BVH = brute force, ESS, ray order,
+tile shape, persistent launch, batched views)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_07782_amd import inputs
+
+from helpers import gpu_render, oracle_opts, renderer_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _opts(**kw):
+    from paper_2509_07782_amd.render import RenderOptions
+    return RenderOptions(**kw)
+
+
+def test_build_structure(torch_cuda):
+    """Sorted keys, stable permutation of the active Gaussians, conservative
+    leaf boxes (Supp. B half-lengths) and a tree whose boxes nest and whose
+    leaves are each reached once."""
+    sc = inputs.make_scene("cluster", 5000, 3)
+    sc["density"][:7] = 0.001                       # below sigma_eps: inactive
+    sc["quats"][7:9] = 0.0                          # zero quaternion: inactive
+    sc["means"][9, 0] = np.nan                      # non-finite: inactive
+    r, _ = renderer_for(sc)
+    keys, perm, aabb, nodes, na = r.bvh.debug()
+    k2, act, R, half = oracle.gaussians(sc, np.float32(0.01))
+    assert na == act.sum() == 5000 - 10
+    assert np.all(np.diff(keys[:na].astype(np.float64)) >= 0)
+    assert sorted(perm[:na].tolist()) == np.nonzero(act)[0].tolist()
+    assert sorted(perm.tolist()) == list(range(5000))
+    eq = np.nonzero(keys[1:na] == keys[:na - 1])[0]
+    assert np.all(perm[eq] < perm[eq + 1])          # stable among equal keys
+    mu = sc["means"][perm[:na]].astype(np.float64)
+    L = half[perm[:na]]
+    assert np.all(aabb[:na, :3] <= mu - L + 1e-7) and np.all(aabb[:na, 3:] >= mu + L - 1e-7)
+    # walk the tree
+    seen = np.zeros(na, int)
+    stack = [(0, None)]
+    while stack:
+        node, box = stack.pop()
+        nd = nodes[node]
+        ch = nd[[3, 7]].view(np.int32)
+        boxes = [np.r_[nd[0:3], nd[4:7]], np.r_[nd[8:11], nd[12:15]]]
+        for c, b in zip(ch, boxes):
+            if box is not None:
+                assert np.all(b[:3] >= box[:3]) and np.all(b[3:] <= box[3:])
+            if c < 0:
+                leaf = ~c
+                seen[leaf] += 1
+                assert np.array_equal(b, aabb[leaf])
+            else:
+                stack.append((c, b))
+    assert np.all(seen == 1)
+
+
+def test_config1_brute_force_matches_oracle(torch_cuda):
+    """1k Gaussians, 64x64, fixed step 0.01, no skipping, brute force: every
+    pixel within 1e-4 of the FP64 oracle."""
+    sc = inputs.config_scene(1)
+    cam = inputs.config_cameras(1)[0]
+    r, _ = renderer_for(sc)
+    for teps in (0.0, 1e-4):
+        o = _opts(dt=0.01, ess=0, t_eps=teps, brute_force=True, ray_order=1)
+        rgb, T = gpu_render(r, [cam], o)
+        orgb, oT, ost, _ = oracle.render(sc, cam, oracle_opts(o))
+        assert (ost[:, 0] > 0).mean() > 0.5
+        err = np.abs(rgb - orgb).max()
+        assert err <= 1e-4, err
+        assert np.abs(T - oT).max() <= 1e-4
+
+
+def test_bvh_equals_brute_force_bitwise(torch_cuda):
+    """Images and per-segment hit sets of the BVH path equal brute force bit
+    for bit (same leaves, same order)."""
+    import torch
+    for kind, n, deg, dt in (("uniform", 1000, 0, 0.01), ("cluster", 20000, 3, 0.005)):
+        sc = inputs.make_scene(kind, n, 17, sh_degree=deg)
+        cam = inputs.look_at_camera(67, 45, (0.2, 0.1, 2.9))
+        r, _ = renderer_for(sc)
+        for ess in (0, 1):
+            ob = _opts(dt=dt, ess=ess, t_eps=1e-4, brute_force=True)
+            ov = _opts(dt=dt, ess=ess, t_eps=1e-4, brute_force=False)
+            a = gpu_render(r, [cam], ob)
+            b = gpu_render(r, [cam], ov)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        pix = torch.arange(0, 67 * 45, 7, dtype=torch.int32, device="cuda")
+        cap = 4096
+        outs = []
+        for bf in (True, False):
+            o = _opts(dt=dt, ess=1, t_eps=1e-4, brute_force=bf)
+            seg_a = torch.zeros((pix.numel(), cap), device="cuda")
+            ids = torch.full((pix.numel(), cap), -1, dtype=torch.int32, device="cuda")
+            cnt = torch.zeros(pix.numel(), dtype=torch.int32, device="cuda")
+            from paper_2509_07782_amd import lib
+            lib.dump_hits(r.ctx, r.bvh, cam, o, pix, cap, seg_a, ids, cnt)
+            torch.cuda.synchronize()
+            outs.append((seg_a.cpu().numpy(), ids.cpu().numpy(), cnt.cpu().numpy()))
+        assert outs[0][2].max() <= cap and outs[0][2].sum() > 0
+        assert np.array_equal(outs[0][2], outs[1][2])
+        assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][0], outs[1][0])
+
+
+@pytest.fixture(scope="module")
+def cluster_setup(torch_cuda):
+    sc = inputs.make_scene("cluster", 20000, 23)
+    cam = inputs.look_at_camera(67, 45, (0.3, 0.2, 2.8))
+    r, params = renderer_for(sc)
+    return sc, cam, r
+
+
+def test_ess_bit_identical(cluster_setup):
+    sc, cam, r = cluster_setup
+    a = gpu_render(r, [cam], _opts(dt=0.005, ess=0, t_eps=1e-4))
+    b = gpu_render(r, [cam], _opts(dt=0.005, ess=1, t_eps=1e-4))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_ray_order_tiles_persistent_bit_identical(cluster_setup):
+    sc, cam, r = cluster_setup
+    ref = gpu_render(r, [cam], _opts(dt=0.005, ray_order=0))
+    for tw, th in ((8, 8), (16, 4), (32, 2), (64, 1), (4, 16)):
+        for pers in (False, True):
+            o = _opts(dt=0.005, ray_order=1, tile_w=tw, tile_h=th, persistent=pers)
+            out = gpu_render(r, [cam], o)
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), (tw, th, pers)
+
+
+def test_cluster_fixed_step_matches_oracle(cluster_setup):
+    """SH degree 3, ESS, fixed step: every pixel within 1e-4 of the oracle,
+    statistics (Q, P, samples, segments) equal on almost every ray."""
+    sc, cam, r = cluster_setup
+    for teps in (0.0, 1e-4):
+        o = _opts(dt=0.005, ess=1, t_eps=teps)
+        rgb, T, st = gpu_render(r, [cam], o, stats=True)
+        orgb, oT, ost, mg = oracle.render(sc, cam, oracle_opts(o))
+        assert (ost[:, 0] > 10).mean() > 0.3
+        err = np.abs(rgb - orgb).max(axis=1)
+        assert err.max() <= 1e-4, (err.max(), mg[err.argmax()])
+        assert np.abs(T - oT).max() <= 1e-4
+        same = np.all(st[:, :4] == ost[:, :4], axis=1)
+        assert same.mean() >= 0.99, same.mean()
+
+
+def test_cluster_adaptive_matches_oracle(cluster_setup):
+    """Adaptive step (Eq. 5) with closest-hit restarts: pixels within 1e-4
+    except rays whose discrete decisions had a near tie in the oracle."""
+    sc, cam, r = cluster_setup
+    for teps in (0.0, 1e-4):
+        o = _opts(adaptive=True, ess=1, t_eps=teps)
+        rgb, T = gpu_render(r, [cam], o)
+        orgb, oT, ost, mg = oracle.render(sc, cam, oracle_opts(o))
+        err = np.abs(rgb - orgb).max(axis=1)
+        bad = err > 1e-4
+        assert bad.mean() <= 0.002, (bad.sum(), err.max())
+        assert np.all(mg[bad] < 1e-5), mg[bad]
+
+
+def test_multi_view_batch_equals_separate(torch_cuda):
+    sc = inputs.make_scene("cluster", 20000, 29)
+    cams = [inputs.look_at_camera(40 + 7 * i, 30 + 5 * i, (0.4 * i - 0.4, 0.1, 2.9)) for i in range(3)]
+    r, _ = renderer_for(sc)
+    o = _opts(dt=0.005)
+    full = gpu_render(r, cams, o)
+    off = 0
+    for c in cams:
+        one = gpu_render(r, [c], o)
+        n = c.width * c.height
+        assert np.array_equal(full[0][off:off + n], one[0]) and np.array_equal(full[1][off:off + n], one[1])
+        off += n
+
+
+def test_invalid_arguments_rejected(torch_cuda):
+    import torch
+    from paper_2509_07782_amd import lib
+    sc = inputs.make_scene("uniform", 100, 1)
+    r, _ = renderer_for(sc)
+    cam = inputs.look_at_camera(8, 8, (0, 0, 3))
+    rgb = torch.empty((64, 3), device="cuda")
+    T = torch.empty(64, device="cuda")
+    for bad in (dict(n_s=3), dict(dt=0.0), dict(ess=5), dict(ray_order=1, tile_w=8, tile_h=4),
+                dict(adaptive=True, dt_min=0.02, dt_max=0.01)):
+        with pytest.raises(lib.RgxError):
+            lib.render_forward(r.ctx, r.bvh, [cam], _opts(**bad), rgb, T)
+    badcam = inputs.look_at_camera(8, 8, (0, 0, 3), t_near=2.0, t_far=1.0)
+    with pytest.raises(lib.RgxError):
+        lib.render_forward(r.ctx, r.bvh, [badcam], _opts(), rgb, T)
+    assert r.ctx.error_flags() == 0
