@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000, help="Gaussians (workload: 1M)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=64)
-    ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--persistent", type=int, default=1)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device copy of this size first (HBM counter calibration)")
     ap.add_argument("--tile", default="8x8")
     ap.add_argument("--json-out", default=None)
     return ap.parse_args()
@@ -69,6 +71,17 @@ def main():
     from paper_2509_07782_amd.render import RenderOptions, Renderer, render
 
     lib.load()
+    if args.copy_probe_mb:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale between counter units and bytes moved
+        nbytes = args.copy_probe_mb << 20
+        src = torch.ones(nbytes // 4, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nbytes} bytes read and written")
+        del src, dst
     t0 = time.time()
     scene = inputs.config_scene(3, n=args.n)
     cams = inputs.config_cameras(3)

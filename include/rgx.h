@@ -99,6 +99,8 @@ typedef struct {
   int32_t ray_order;         /* 0: scanline rows of 64 rays; 1: tiles in Morton order */
   int32_t tile_w, tile_h;    /* tile shape for ray_order 1, tile_w*tile_h = 64 (0: 8x8) */
   int32_t persistent;        /* 1: persistent launch popping tiles from a device queue */
+  int32_t window_segments;   /* initial depth-window length, in longest segments (0: 2);
+                                tuning only, never changes results */
   float bg[3];               /* background colour added with the final transmittance */
 } rgx_render_opts;
 
@@ -115,6 +117,8 @@ enum {
   RGX_STAT_SEGMENTS,     /* non-empty segments processed */
   RGX_STAT_CLOSEST,      /* closest-hit queries */
   RGX_STAT_BOX_ONLY,     /* leaves whose AABB met the segment but whose ellipsoid did not */
+  RGX_STAT_NODES,        /* BVH nodes loaded by the wave for the segment collections */
+  RGX_STAT_LEAVES,       /* leaves the wave visited for the segment collections */
   RGX_NSTAT = 8
 };
 

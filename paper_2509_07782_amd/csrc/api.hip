@@ -18,7 +18,8 @@ using namespace rgx;
 
 static_assert(RGX_STAT_Q == ST_Q && RGX_STAT_P == ST_P && RGX_STAT_SAMPLES == ST_SAMPLES &&
                   RGX_STAT_SEGMENTS == ST_SEGMENTS && RGX_STAT_CLOSEST == ST_CLOSEST &&
-                  RGX_STAT_BOX_ONLY == ST_BOX_ONLY && RGX_NSTAT == kNStat,
+                  RGX_STAT_BOX_ONLY == ST_BOX_ONLY && RGX_STAT_NODES == ST_NODES &&
+                  RGX_STAT_LEAVES == ST_LEAVES && RGX_NSTAT == kNStat,
               "stat slots");
 
 namespace {
@@ -46,7 +47,7 @@ struct rgx_bvh {
   int morton_bits = 21;
   int sorted_sel = 0;
   DevBuf geom_user, aabb_user, aux_user, aux, active, bounds, counters, keys0, keys1, vals0, vals1, hist, geom,
-      aabb, col, nodes, node_box, parent, visit, acc;
+      aabb, col, nodes, seg, parent, acc;
 };
 
 static rgx_status fail(rgx_context *ctx, rgx_status s, const std::string &msg) {
@@ -130,7 +131,7 @@ void rgx_bvh_destroy(rgx_bvh *b) {
   if (!b) return;
   DevBuf *all[] = {&b->geom_user, &b->aabb_user, &b->aux_user, &b->aux, &b->active, &b->bounds, &b->counters, &b->keys0,
                    &b->keys1, &b->vals0, &b->vals1, &b->hist, &b->geom, &b->aabb, &b->col,
-                   &b->nodes, &b->node_box, &b->parent, &b->visit, &b->acc};
+                   &b->nodes, &b->seg, &b->parent, &b->acc};
   for (DevBuf *d : all) release(*d);
   delete b;
 }
@@ -182,9 +183,10 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   ENS(aabb, (size_t)n * 6 * 4);
   ENS(col, (size_t)n * col_stride * 4);
   ENS(nodes, nodes_n * 16 * 4);
-  ENS(node_box, nodes_n * 6 * 4);
+  int64_t P = 1;
+  while (P < n) P <<= 1;
+  ENS(seg, (size_t)(2 * P) * 6 * 4);
   ENS(parent, (size_t)(2 * n) * 4);
-  ENS(visit, nodes_n * 4);
   ENS(acc, (size_t)n * kAccFloats * 4);
 #undef ENS
   if (e != hipSuccess) {
@@ -212,8 +214,8 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   a.sort_hist = (uint32_t *)b->hist.p;
   a.sorted_sel = &b->sorted_sel;
   a.geom = (float *)b->geom.p; a.aabb = (float *)b->aabb.p; a.col = (float *)b->col.p;
-  a.nodes = (float *)b->nodes.p; a.node_box = (float *)b->node_box.p;
-  a.parent = (int32_t *)b->parent.p; a.visit = (int32_t *)b->visit.p;
+  a.nodes = (float *)b->nodes.p; a.seg = (float *)b->seg.p;
+  a.parent = (int32_t *)b->parent.p;
   e = launch_build(a, stream);
   if (e == hipSuccess) e = launch_fill(b->acc.p, n * kAccFloats, 0u, stream);
   if (e != hipSuccess) {
@@ -281,6 +283,9 @@ static rgx_status make_opts(rgx_context *ctx, const rgx_bvh *b, const rgx_render
   m.tile_h = th;
   m.tile_w_log2 = ilog2(tw);
   m.persistent = o->persistent ? 1 : 0;
+  if (o->window_segments < 0 || o->window_segments > 64)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "window_segments must be 0..64");
+  m.window_segments = o->window_segments ? o->window_segments : 2;
   for (int i = 0; i < 3; i++) m.bg[i] = o->bg[i];
   m.sh_k = b->sh_k;
   m.col_stride = b->col_stride;
@@ -380,8 +385,8 @@ static LaunchShape shape_for(rgx_context *ctx, const MarchOpts &m, int n_tiles) 
   LaunchShape ls;
   ls.queue = ctx->queue;
   ls.error_flag = ctx->queue + 8;
-  const int nb = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  ls.grid = m.persistent ? std::min(nb, ctx->n_cu * 8) : nb;
+  // one wave (one 64-ray tile) per workgroup
+  ls.grid = m.persistent ? std::min(n_tiles, ctx->n_cu * 12) : n_tiles;
   if (ls.grid < 1) ls.grid = 1;
   return ls;
 }

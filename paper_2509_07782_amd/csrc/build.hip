@@ -1,6 +1,6 @@
 // Acceleration-structure build: per-Gaussian preprocessing, Z-order (Morton)
-// keys, a stable LSD radix sort, the Z-ordered pack, and a Karras LBVH with a
-// bottom-up refit.  Every size follows from N on the host; the number of
+// keys, a stable LSD radix sort, the Z-ordered pack, and a Karras LBVH whose
+// node boxes come from range unions over a segment tree of the leaf boxes.  Every size follows from N on the host; the number of
 // active Gaussians stays on the device, so the whole build is asynchronous.
 #include "common.hpp"
 #include "internal.hpp"
@@ -271,6 +271,52 @@ __global__ __launch_bounds__(256) void k_pack(int64_t n, const int32_t *__restri
   for (int k = 3 * sh_k; k < col_stride; k++) cd[k] = 0.0f;
 }
 
+// Node boxes without inter-thread synchronisation: a segment tree (heap
+// layout, P leaves, P a power of two) over the Z-ordered leaf boxes gives the
+// union of any leaf range in O(log P) reads; every internal node's child
+// boxes are the unions of its two child ranges.
+__global__ __launch_bounds__(256) void k_seg_leaves(int64_t P, const int32_t *__restrict__ counters,
+                                                    const float *__restrict__ aabb,
+                                                    float *__restrict__ seg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const int n = counters[0];
+  float *d = seg + 6 * (size_t)(P + i);
+  if (i < n) {
+    for (int k = 0; k < 6; k++) d[k] = aabb[6 * i + k];
+  } else {
+    for (int k = 0; k < 3; k++) { d[k] = __builtin_huge_valf(); d[3 + k] = -__builtin_huge_valf(); }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_seg_level(int64_t lo, int64_t hi, float *__restrict__ seg) {
+  const int64_t k = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= hi) return;
+  const float *a = seg + 6 * (size_t)(2 * k), *b = seg + 6 * (size_t)(2 * k + 1);
+  float *d = seg + 6 * (size_t)k;
+  for (int c = 0; c < 3; c++) { d[c] = fminf(a[c], b[c]); d[3 + c] = fmaxf(a[3 + c], b[3 + c]); }
+}
+
+// Union of the boxes of leaves [l, r] (inclusive).
+__device__ __forceinline__ void seg_query(const float *__restrict__ seg, int64_t P, int64_t l,
+                                          int64_t r, float *box) {
+  for (int c = 0; c < 3; c++) { box[c] = __builtin_huge_valf(); box[3 + c] = -__builtin_huge_valf(); }
+  l += P;
+  r += P + 1;
+  while (l < r) {
+    if (l & 1) {
+      const float *x = seg + 6 * (size_t)l++;
+      for (int c = 0; c < 3; c++) { box[c] = fminf(box[c], x[c]); box[3 + c] = fmaxf(box[3 + c], x[3 + c]); }
+    }
+    if (r & 1) {
+      const float *x = seg + 6 * (size_t)(--r);
+      for (int c = 0; c < 3; c++) { box[c] = fminf(box[c], x[c]); box[3 + c] = fmaxf(box[3 + c], x[3 + c]); }
+    }
+    l >>= 1;
+    r >>= 1;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Karras LBVH over the sorted keys of the active Gaussians.  Internal node i
 // covers a key range with i at one end; duplicate keys are split by index.
@@ -285,9 +331,9 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
                                                         const int32_t *__restrict__ counters,
                                                         const uint64_t *__restrict__ keys,
                                                         const float *__restrict__ aabb,
+                                                        const float *__restrict__ seg, int64_t P,
                                                         float4 *__restrict__ nodes,
-                                                        int32_t *__restrict__ parent,
-                                                        int32_t *__restrict__ visit) {
+                                                        int32_t *__restrict__ parent) {
   const int n = counters[0];
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= n_max) return;
@@ -301,7 +347,6 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
     return;
   }
   if (i >= n - 1) return;
-  visit[i] = 0;
   if (i == 0) parent[0] = -1;
   const int d = (lcp(keys, n, i, i + 1) - lcp(keys, n, i, i - 1)) >= 0 ? 1 : -1;
   const int dmin = lcp(keys, n, i, i - d);
@@ -326,53 +371,14 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
   const int right = (hi == gamma + 1) ? ~(gamma + 1) : gamma + 1;
   if (left < 0) parent[(n - 1) + gamma] = i; else parent[left] = i;
   if (right < 0) parent[(n - 1) + gamma + 1] = i; else parent[right] = i;
+  float bl[6], br[6];
+  seg_query(seg, P, lo, gamma, bl);
+  seg_query(seg, P, gamma + 1, hi, br);
   float4 *nd = nodes + 4 * (size_t)i;
-  nd[0].w = __int_as_float(left);
-  nd[1].w = __int_as_float(right);
-}
-
-// Bottom-up refit: the second thread to reach a node writes both child boxes
-// into it and its union into node_box, then continues upward.
-__device__ __forceinline__ float load_relaxed(const float *p) {
-  return __int_as_float(__hip_atomic_load(reinterpret_cast<const int *>(p), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT));
-}
-
-__global__ __launch_bounds__(256) void k_lbvh_refit(int64_t n_max, const int32_t *__restrict__ counters,
-                                                    const float *__restrict__ aabb,
-                                                    float4 *__restrict__ nodes,
-                                                    const int32_t *__restrict__ parent,
-                                                    int32_t *__restrict__ visit,
-                                                    float *__restrict__ node_box) {
-  const int n = counters[0];
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < 2 || tid >= n) return;
-  int node = parent[(n - 1) + (int)tid];
-  for (int depth = 0; node >= 0 && node < n - 1 && depth < 256; depth++) {
-    __threadfence();
-    if (atomicAdd(&visit[node], 1) == 0) return;   // the sibling is still on its way
-    __threadfence();
-    float4 *nd = nodes + 4 * (size_t)node;
-    const int ch[2] = {__float_as_int(nd[0].w), __float_as_int(nd[1].w)};
-    float b[2][6];
-    for (int c = 0; c < 2; c++) {
-      const float *src = ch[c] < 0 ? aabb + 6 * (size_t)(~ch[c]) : node_box + 6 * (size_t)ch[c];
-      for (int k = 0; k < 6; k++) b[c][k] = load_relaxed(src + k);
-    }
-    nd[0] = make_float4(b[0][0], b[0][1], b[0][2], __int_as_float(ch[0]));
-    nd[1] = make_float4(b[0][3], b[0][4], b[0][5], __int_as_float(ch[1]));
-    nd[2] = make_float4(b[1][0], b[1][1], b[1][2], 0.0f);
-    nd[3] = make_float4(b[1][3], b[1][4], b[1][5], 0.0f);
-    float* ob = node_box + 6 * (size_t)node;
-    for (int k = 0; k < 3; k++) {
-      __hip_atomic_store(reinterpret_cast<int *>(ob + k), __float_as_int(fminf(b[0][k], b[1][k])),
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(reinterpret_cast<int *>(ob + 3 + k),
-                         __float_as_int(fmaxf(b[0][3 + k], b[1][3 + k])), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    node = parent[node];
-  }
+  nd[0] = make_float4(bl[0], bl[1], bl[2], __int_as_float(left));
+  nd[1] = make_float4(bl[3], bl[4], bl[5], __int_as_float(right));
+  nd[2] = make_float4(br[0], br[1], br[2], 0.0f);
+  nd[3] = make_float4(br[3], br[4], br[5], 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -401,12 +407,13 @@ hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
   k_pack<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.vals[cur], a.geom_user, a.aabb_user,
                                        a.aux_user, a.sh, a.sh_k, a.col_stride, a.geom, a.aabb,
                                        a.aux, a.col);
-  k_lbvh_hierarchy<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.keys[cur], a.aabb,
-                                                 reinterpret_cast<float4 *>(a.nodes), a.parent,
-                                                 a.visit);
-  k_lbvh_refit<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.aabb,
-                                             reinterpret_cast<float4 *>(a.nodes), a.parent,
-                                             a.visit, a.node_box);
+  int64_t P = 1;
+  while (P < n) P <<= 1;
+  k_seg_leaves<<<nblk(P, 256), 256, 0, st>>>(P, a.counters, a.aabb, a.seg);
+  for (int64_t lo = P >> 1; lo >= 1; lo >>= 1)
+    k_seg_level<<<nblk(lo, 256), 256, 0, st>>>(lo, 2 * lo, a.seg);
+  k_lbvh_hierarchy<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.keys[cur], a.aabb, a.seg, P,
+                                                 reinterpret_cast<float4 *>(a.nodes), a.parent);
   return hipGetLastError();
 }
 

@@ -19,8 +19,8 @@ constexpr int32_t kNoChild = INT32_MIN;
 enum GeomSlot { G_MU = 0, G_K2 = 3, G_M = 4, G_SIG = 13, G_L2SIG = 14 };
 
 // per-ray statistics slots (same order as the public RGX_STAT_* enum)
-enum { ST_Q = 0, ST_P, ST_SAMPLES, ST_SEGMENTS, ST_CLOSEST, ST_BOX_ONLY };
-constexpr int kNStatUsed = 6;
+enum { ST_Q = 0, ST_P, ST_SAMPLES, ST_SEGMENTS, ST_CLOSEST, ST_BOX_ONLY, ST_NODES, ST_LEAVES };
+constexpr int kNStatUsed = 8;
 constexpr int kNStat = 8;
 
 struct View {
@@ -49,6 +49,7 @@ struct MarchOpts {
   int32_t ray_order;
   int32_t tile_w, tile_h, tile_w_log2;
   int32_t persistent;
+  int32_t window_segments;
   float bg[3];
   int32_t sh_k;           // SH coefficients per channel
   int32_t col_stride;     // floats per packed colour record
@@ -76,8 +77,10 @@ __device__ __forceinline__ float uniform_float(float v) {
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 // Real SH basis (Condon-Shortley phase, index l^2+l+m) at a unit direction,
-// as polynomials in (x, y, z) for degrees 0..3.
+// as polynomials in (x, y, z) for degrees 0..3; entries m >= k are zero.
 __device__ __forceinline__ void sh_basis(int k, float x, float y, float z, float *Y) {
+#pragma unroll
+  for (int m = 1; m < 16; m++) Y[m] = 0.0f;
   Y[0] = 0.28209479177387814f;
   if (k <= 1) return;
   Y[1] = -0.48860251190291992f * y;
@@ -100,9 +103,14 @@ __device__ __forceinline__ void sh_basis(int k, float x, float y, float z, float
   Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
 }
 
+constexpr float kLog2e = 1.4426950408889634f;
+
+// exp(-x) through the hardware base-2 exponential.
+__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-x * kLog2e); }
+
 // 1 - exp(-x) for x >= 0 without cancellation at small x.
 __device__ __forceinline__ float one_minus_exp_neg(float x) {
-  const float e = __expf(-x);
+  const float e = exp_neg(x);
   const float series = x * (1.0f - x * (0.5f - x * (1.0f / 6.0f)));
   return x < 1e-3f ? series : 1.0f - e;
 }

@@ -22,8 +22,9 @@ struct BuildArgs {
   uint32_t *sort_hist;
   int *sorted_sel;           // (host) which ping-pong buffer holds the result
   // outputs (Z order)
-  float *geom, *aabb, *col, *aux, *nodes, *node_box;
-  int32_t *parent, *visit;
+  float *geom, *aabb, *col, *aux, *nodes;
+  float *seg;                // segment tree of leaf boxes, 2P boxes
+  int32_t *parent;
 };
 hipError_t launch_build(const BuildArgs &a, hipStream_t st);
 

@@ -1,17 +1,32 @@
 // Forward and backward ray marching through the Gaussian field (Sec. 3.1
 // Eq. 1-3; Sec. 3.2 Algorithm 1, Eq. 4-5).
 //
-// Execution model: one wave64 owns one ray tile (64 rays).  The wave walks the
-// LBVH as a packet: a node is entered when any active lane's ray meets one of
-// its child boxes over that lane's own interval, and the traversal stack is
-// wave-uniform, held one entry per lane in two VGPRs (writelane/readlane).
-// Node and Gaussian records are read at wave-uniform addresses through the
-// scalar cache.  Leaves are met in left-to-right (= Z order) order whatever
-// subset of the tree a packet visits, so every lane accumulates its samples
-// in the same order under the BVH, under brute force, for any tile shape and
-// ray order, which makes those images bit-identical.
+// Execution model: one wave64 (one workgroup) owns one tile of 64 rays.  Each
+// lane marches its ray segment by segment (Alg. 1).  Candidate Gaussians come
+// from a per-wave window list: for a depth window covering several segments of
+// every live lane, a node-parallel walk of the LBVH gathers the Gaussians
+// whose ellipsoid chord meets some lane's window, each with the mask of those
+// lanes and its extreme chord ends (see collect_window).  Every segment then
+// runs over that list with a wave-uniform depth pre-check, so one BVH walk
+// serves several segments and its memory latency is spread over 64
+// independent node fetches per round.  Geometry and colour records of the
+// Gaussian being evaluated are read at wave-uniform addresses through the
+// scalar cache.  Closest-hit restarts beyond the window use a depth-first
+// packet traversal.
+//
+// Every ray meets its Gaussians in Z-index order (the window list is sorted,
+// the depth-first walk visits leaves left to right, brute force counts up),
+// whatever packet, window, tile shape or ray order is used; the images of all
+// these variants are therefore bit-identical.
 #include "common.hpp"
 #include "internal.hpp"
+
+#ifndef RGX_NODE_VLOAD
+#define RGX_NODE_VLOAD 0
+#endif
+#ifndef RGX_REC_VLOAD
+#define RGX_REC_VLOAD 0
+#endif
 
 namespace rgx {
 
@@ -50,8 +65,20 @@ struct Gauss {
   float sig, l2sig;
 };
 
+// Uniform zero held in a VGPR: an address offset by it is loaded through the
+// vector memory path (L1/TA) instead of the scalar cache.
+__device__ __forceinline__ int vgpr_zero() {
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+
 __device__ __forceinline__ Gauss load_gauss(const float *geom, int j) {
+#if RGX_REC_VLOAD
+  const vf4 *p = reinterpret_cast<const vf4 *>(geom) + 4 * j + vgpr_zero();
+#else
   cfloat4p p = as_const4(geom) + 4 * j;
+#endif
   const vf4 a = p[0], b = p[1], c = p[2], d = p[3];
   Gauss g;
   g.mx = a.x; g.my = a.y; g.mz = a.z; g.k2 = a.w;
@@ -85,11 +112,12 @@ __device__ __forceinline__ Chord chord(const Gauss &g, const Ray &r) {
   Chord c;
   c.A = fmaf(dpx, dpx, fmaf(dpy, dpy, dpz * dpz));
   const float B = fmaf(opx, dpx, fmaf(opy, dpy, opz * dpz));
-  c.ts = -B / c.A;
+  const float rA = __builtin_amdgcn_rcpf(c.A);
+  c.ts = -B * rA;
   const float px = fmaf(c.ts, dpx, opx), py = fmaf(c.ts, dpy, opy), pz = fmaf(c.ts, dpz, opz);
   c.h2 = fmaf(px, px, fmaf(py, py, pz * pz));
   c.exists = c.h2 <= g.k2;
-  const float w = sqrtf(fmaxf(g.k2 - c.h2, 0.0f) / c.A);
+  const float w = __builtin_amdgcn_sqrtf(fmaxf(g.k2 - c.h2, 0.0f) * rA);
   c.tin = c.ts - w;
   c.tout = c.ts + w;
   return c;
@@ -131,63 +159,61 @@ struct WaveStack {
   }
 };
 
-// Packet traversal in left-to-right leaf order.  `lo`/`hi` are per-lane
-// interval references (hi may shrink inside `leaf`).  Leaves whose box meets
-// some lane's interval are passed to leaf(j) with j wave-uniform.
-template <class Leaf>
-__device__ __forceinline__ void traverse(const SceneDev &s, int n_active, const Ray &r,
-                                         const float &lo, const float &hi, int32_t *err,
-                                         Leaf &&leaf) {
-  if (n_active <= 0) return;
+// Packet traversal in left-to-right leaf order, as an iterator: next() returns
+// the next leaf (wave-uniform) whose box meets some active lane's interval
+// [lo, hi], or -1.  A left leaf is returned at once and the right child waits
+// on the stack, so leaves come out in Z order whatever the packet prunes.
+// Brute force enumerates every active Gaussian in the same order.
+struct LeafIter {
   WaveStack st;
-  st.lane = __lane_id();
-  int node = 0;
-  const int n_inner = n_active > 1 ? n_active - 1 : 1;
-  // a valid tree visits each of its n_inner nodes at most once
-  for (int visits = 0;; visits++) {
-    if (visits > n_inner) { if (err) *err = 2; return; }
-    cfloat4p np = as_const4(s.nodes) + 4 * node;
-    const vf4 a = np[0], b = np[1], c = np[2], d = np[3];
-    const int cl = __float_as_int(a.w), cr = __float_as_int(b.w);
-    // child references must stay inside the structure
-    const bool bad = (cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
-                     (cr != kNoChild && (cr >= 0 ? cr >= n_inner : ~cr >= n_active));
-    if (bad) { if (err) *err = 3; return; }
-    bool hl = ballot(box_hit(a.x, a.y, a.z, b.x, b.y, b.z, r, lo, hi)) != 0;
-    bool hr = cr != kNoChild && ballot(box_hit(c.x, c.y, c.z, d.x, d.y, d.z, r, lo, hi)) != 0;
-    if (hl && cl < 0) { leaf(~cl); hl = false; }
-    if (hr && cr < 0 && !hl) { leaf(~cr); hr = false; }
-    if (hl) {
-      if (hr && !st.push(cr)) { if (err) *err = 1; return; }
-      node = cl;
-      continue;
-    }
-    if (hr) { node = cr; continue; }
-    bool found = false;
-    while (st.sp > 0) {
-      const int v = st.pop();
-      if (v < 0) { leaf(~v); continue; }
-      node = v;
-      found = true;
-      break;
-    }
-    if (!found) return;
+  int node, visits, n_inner, n_active, next_brute;
+  bool brute;
+  __device__ __forceinline__ void init(int n_act, bool brute_force) {
+    st.lane = __lane_id();
+    st.sp = 0;
+    n_active = n_act;
+    n_inner = n_act > 1 ? n_act - 1 : 1;
+    node = n_act > 0 ? 0 : -1;
+    visits = 0;
+    brute = brute_force;
+    next_brute = 0;
   }
-}
-
-// Brute force: every active Gaussian in Z order (the hit-set reference).
-template <class Leaf>
-__device__ __forceinline__ void brute_all(int n_active, Leaf &&leaf) {
-  for (int j = 0; j < n_active; j++) leaf(j);
-}
-
-template <class Leaf>
-__device__ __forceinline__ void for_each_candidate(const SceneDev &s, const MarchOpts &op,
-                                                   int n_active, const Ray &r, const float &lo,
-                                                   const float &hi, int32_t *err, Leaf &&leaf) {
-  if (op.brute_force) brute_all(n_active, leaf);
-  else traverse(s, n_active, r, lo, hi, err, leaf);
-}
+  __device__ __forceinline__ int next(const SceneDev &s, const Ray &r, float lo, float hi,
+                                      int32_t *err) {
+    if (brute) return next_brute < n_active ? next_brute++ : -1;
+    for (;;) {
+      if (node < 0) {
+        if (st.sp == 0) return -1;
+        const int v = st.pop();
+        if (v < 0) return ~v;
+        node = v;
+      }
+      // a valid tree loads each of its n_inner nodes at most once
+      if (++visits > n_inner) { if (err) *err = 2; st.sp = 0; node = -1; return -1; }
+#if RGX_NODE_VLOAD
+      const vf4 *np = reinterpret_cast<const vf4 *>(s.nodes) + 4 * node + vgpr_zero();
+      const vf4 a = np[0], b = np[1], c = np[2], d = np[3];
+      const int cl = uniform_int(__float_as_int(a.w)), cr = uniform_int(__float_as_int(b.w));
+#else
+      cfloat4p np = as_const4(s.nodes) + 4 * node;
+      const vf4 a = np[0], b = np[1], c = np[2], d = np[3];
+      const int cl = __float_as_int(a.w), cr = __float_as_int(b.w);
+#endif
+      const bool bad = (cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
+                       (cr != kNoChild && (cr >= 0 ? cr >= n_inner : ~cr >= n_active));
+      if (bad) { if (err) *err = 3; st.sp = 0; node = -1; return -1; }
+      const bool hl = ballot(box_hit(a.x, a.y, a.z, b.x, b.y, b.z, r, lo, hi)) != 0;
+      const bool hr = cr != kNoChild && ballot(box_hit(c.x, c.y, c.z, d.x, d.y, d.z, r, lo, hi)) != 0;
+      if (hr && !st.push(cr)) { if (err) *err = 1; st.sp = 0; node = -1; return -1; }
+      if (hl) {
+        if (cl >= 0) { node = cl; continue; }
+        node = -1;
+        return ~cl;
+      }
+      node = -1;
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Work distribution: global tile index -> view, pixel, output ray.
@@ -270,7 +296,7 @@ __device__ __forceinline__ void sample_positions(bool grid, int seg_i, float a, 
 // Eq. 5 with d_i = a (unit direction from the camera centre).
 __device__ __forceinline__ float adaptive_dt(const MarchOpts &op, float a, float T) {
   const float base = fmaxf(a * op.inv_beta, op.dt_min);
-  const float v = base * exp2f(-__log2f(T) * (1.0f / 3.0f));
+  const float v = base * __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(T) * (1.0f / 3.0f));
   return v < op.dt_max ? v : op.dt_max;
 }
 
@@ -281,41 +307,454 @@ struct SegState {
   float a, cl_lo;
 };
 
+
+// The N_S sample weights of one Gaussian for one lane:
+// w_k = sigma~ exp(-q(t_k)/2) if q(t_k) <= k^2 else 0.
+template <int NS>
+__device__ __forceinline__ void sample_weights(const Gauss &g, const Chord &c, const float *ts,
+                                               float *w) {
+#pragma unroll
+  for (int k = 0; k < NS; k++) {
+    const float u = ts[k] - c.ts;
+    const float q = fmaf(c.A * u, u, c.h2);
+    const float e = __builtin_amdgcn_exp2f(fmaf(-q, kHalfLog2e, g.l2sig));
+    w[k] = q <= g.k2 ? e : 0.0f;
+  }
+}
+
+// Segment bounds [a, b], step and sample positions of a live lane.
+template <int NS>
+__device__ __forceinline__ bool segment(const MarchOpts &op, bool grid, const SegState &ss,
+                                        float tn, float T, float &a, float &b, float &dt,
+                                        float *ts) {
+  a = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
+  dt = op.adaptive ? adaptive_dt(op, a, T) : op.dt;
+  b = grid ? fmaf((float)((ss.seg_i + 1) * NS), op.dt, tn) : fmaf((float)NS, dt, a);
+  sample_positions<NS>(grid, ss.seg_i, a, dt, tn, ts);
+  return b > a;
+}
+
+// Restart at a closest hit t: on the fixed grid the segment holding t (never
+// going back), otherwise t itself.
+__device__ __forceinline__ void restart_at(const MarchOpts &op, float tn, float dS, float t,
+                                           SegState &ss) {
+  if (!op.adaptive && op.ess == 1) ss.seg_i = max(ss.seg_i, (int)floorf((t - tn) / dS));
+  else ss.a = t;
+}
+
+// Next segment after [a, b]: the following one, or after an empty segment
+// with skipping on, the closest hit `best` (kInf: unknown here -> query).
+__device__ __forceinline__ void step_after(const MarchOpts &op, bool grid, bool nonempty, float best,
+                                           float tn, float dS, float b, SegState &ss) {
+  if (grid) ss.seg_i += 1;
+  else ss.a = b;
+  if (nonempty || !op.ess) return;
+  if (best < kInf) restart_at(op, tn, dS, best, ss);
+  else { ss.pending = true; ss.cl_lo = b; }
+}
+
+// Cross-lane helpers (gfx950): v_permlane32_swap / v_permlane16_swap exchange
+// halves / rows between two registers; DPP row and quad permutes.
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int H, int CTRL>
+__device__ __forceinline__ void dpp_stage(float *x, int lane) {
+  const bool up = (lane & H) != 0;
+#pragma unroll
+  for (int i = 0; i < H; i++) {
+    const float keep = up ? x[i + H] : x[i];
+    const float send = up ? x[i] : x[i + H];
+    x[i] = keep + dpp<CTRL>(send);
+  }
+}
+
+// Reduce-scatter over the wave of the 64 gradient slots of one Gaussian:
+// slots [0,16) are g[0..15]; slot 16 + 16 ch + m is Y[m] * dc[ch] (SH
+// coefficient m of channel ch).  Returns, in lane L, the wave total of slot L.
+// Slot index i and its partners i+16, i+32, i+48 meet in x[i] after one
+// permlane32 and one permlane16 exchange; four in-row DPP stages (mirror,
+// half mirror, quad xor 2, quad xor 1) then split the 16 rows' values.
+__device__ __forceinline__ float wave_reduce_slots(const float *g, const float *Y, float dc0,
+                                                   float dc1, float dc2, int lane) {
+  float x[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++)
+    x[i] = swap16_sum(swap32_sum(g[i], Y[i] * dc1), swap32_sum(Y[i] * dc0, Y[i] * dc2));
+  dpp_stage<8, 0x140>(x, lane);   // row_mirror: lane p <-> 15 - p
+  dpp_stage<4, 0x141>(x, lane);   // row_half_mirror: p <-> 7 - p within 8
+  dpp_stage<2, 0x4e>(x, lane);    // quad_perm [2,3,0,1]
+  dpp_stage<1, 0xb1>(x, lane);    // quad_perm [1,0,3,2]
+  return x[0];
+}
+
 // Closest hit (Alg. 1 ClosestHit, Eq. 4) for the lanes with `pending` set:
 // min over Gaussians whose chord meets [cl_lo, t_far] of max(t_in, cl_lo).
+// Depth-first packet traversal; the shrinking per-lane bound prunes.
 __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts &op, int n_active,
                                              const Ray &r, float tn, float tf, float dS,
                                              SegState &ss, int32_t *err, int32_t *st_closest) {
   if (ballot(ss.pending) == 0) return;
-  float lo = ss.pending ? ss.cl_lo : kInf;
+  const float lo = ss.pending ? ss.cl_lo : kInf;
   float hi = ss.pending ? tf : -kInf;
   float best = kInf;
-  for_each_candidate(s, op, n_active, r, lo, hi, err, [&](int j) {
+  LeafIter it;
+  it.init(n_active, op.brute_force);
+  for (int j; (j = it.next(s, r, lo, hi, err)) >= 0;) {
     const Gauss g = load_gauss(s.geom, j);
     const Chord c = chord(g, r);
     if (c.exists && c.tin <= hi && c.tout >= lo) {
       best = fminf(best, fmaxf(c.tin, lo));
       hi = fminf(hi, best);
     }
-  });
+  }
   if (ss.pending) {
     if (st_closest) (*st_closest)++;
     if (!(best < kInf)) ss.alive = false;
-    else if (!op.adaptive && op.ess == 1) {
-      const int j = (int)floorf((best - tn) / dS);
-      ss.seg_i = max(ss.seg_i, j);
-    } else ss.a = best;
+    else restart_at(op, tn, dS, best, ss);
     ss.pending = false;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Window collection.  For a per-lane depth window [lo, hi] (several segments
+// long) the wave gathers every Gaussian whose chord meets some lane's window,
+// with the 64-bit mask of those lanes and the extreme chord ends over them.
+// The traversal is node-parallel: a FIFO frontier of (node, ray mask) lives
+// in LDS and each round hands up to 64 frontier nodes to the 64 lanes, which
+// load them independently and test both child boxes against the rays of the
+// node's mask.  Leaves are staged and chord-tested 64 at a time.  The list is
+// then sorted by Gaussian (Z) index, so every ray meets its Gaussians in Z
+// order whatever window, packet or traversal produced the list -- the same
+// order as the depth-first fallback and the brute-force enumeration.
+
+constexpr int kRingCap = 256;    // frontier entries (power of two)
+constexpr int kStageCap = 192;   // staged leaves: < 64 left over + 128 per round
+constexpr int kListCap = 512;    // window list entries
+
+struct WaveMem {
+  float rdx[64], rdy[64], rdz[64], rix[64], riy[64], riz[64], rlo[64], rhi[64];
+  union {
+    struct {                       // during collection
+      int32_t ring_id[kRingCap];
+      uint32_t ring_mlo[kRingCap], ring_mhi[kRingCap];
+      int32_t st_id[kStageCap];
+      uint32_t st_mlo[kStageCap], st_mhi[kStageCap];
+    } c;
+    uint64_t order[kListCap];      // afterwards: (Gaussian index << 32 | list slot), sorted
+  } u;
+  int32_t l_id[kListCap];
+  uint32_t l_mlo[kListCap], l_mhi[kListCap];
+  float l_tin[kListCap], l_tout[kListCap];
+  int32_t cnt_box[64];             // per-ray AABB-only leaf count (statistics)
+};
+
+__device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) {
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Lane-local ray r from the wave's LDS copy (origin is wave-uniform).
+__device__ __forceinline__ Ray lds_ray(const WaveMem &M, const Ray &self, int r) {
+  Ray q;
+  q.ox = self.ox; q.oy = self.oy; q.oz = self.oz;
+  q.dx = M.rdx[r]; q.dy = M.rdy[r]; q.dz = M.rdz[r];
+  q.ix = M.rix[r]; q.iy = M.riy[r]; q.iz = M.riz[r];
+  return q;
+}
+
+// Loads one geometry record at a per-lane address (vector memory path).
+__device__ __forceinline__ Gauss load_gauss_lane(const float *geom, int j) {
+  const vf4 *p = reinterpret_cast<const vf4 *>(geom) + 4 * j;
+  const vf4 a = p[0], b = p[1], c = p[2], d = p[3];
+  Gauss g;
+  g.mx = a.x; g.my = a.y; g.mz = a.z; g.k2 = a.w;
+  g.m[0] = b.x; g.m[1] = b.y; g.m[2] = b.z; g.m[3] = b.w;
+  g.m[4] = c.x; g.m[5] = c.y; g.m[6] = c.z; g.m[7] = c.w;
+  g.m[8] = d.x; g.sig = d.y; g.l2sig = d.z;
+  return g;
+}
+
+// Bitonic sort (by Gaussian index) of the window list's order keys in LDS.
+__device__ __forceinline__ void sort_list(WaveMem &M, int lane, int count) {
+  int p2 = 1;
+  while (p2 < count) p2 <<= 1;
+  for (int e = lane; e < p2; e += 64)
+    M.u.order[e] = e < count ? ((uint64_t)(uint32_t)M.l_id[e] << 32) | (uint32_t)e : ~0ull;
+  for (int k = 2; k <= p2; k <<= 1) {
+    for (int j = k >> 1; j >= 1; j >>= 1) {
+      __builtin_amdgcn_wave_barrier();
+      for (int e = lane; e < p2; e += 64) {
+        const int f = e ^ j;
+        if (f > e) {
+          const uint64_t x = M.u.order[e], y = M.u.order[f];
+          const bool up = (e & k) == 0;
+          if ((x > y) == up) { M.u.order[e] = y; M.u.order[f] = x; }
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Returns the number of list entries, -1 when a capacity was exceeded (the
+// caller retries with a shorter window) or -2 on a malformed tree.
+__device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, int lane,
+                              uint64_t rays, int n_active, bool stats, int32_t *err,
+                              int32_t &nodes_out, int32_t &leaves_out) {
+  if (n_active <= 0 || rays == 0) return 0;
+  const int n_inner = n_active > 1 ? n_active - 1 : 1;
+  int head = 0, tail = 1, staged = 0, count = 0, visits = 0;
+  if (lane == 0) {
+    M.u.c.ring_id[0] = 0;
+    M.u.c.ring_mlo[0] = (uint32_t)rays;
+    M.u.c.ring_mhi[0] = (uint32_t)(rays >> 32);
+  }
+  const uint64_t below = lanes_below(lane);
+  for (;;) {
+    __builtin_amdgcn_wave_barrier();
+    const int n = min(64, tail - head);
+    if (n > 0) {
+      int id = 0;
+      uint64_t mk = 0;
+      if (lane < n) {
+        const int slot = (head + lane) & (kRingCap - 1);
+        id = M.u.c.ring_id[slot];
+        mk = join64(M.u.c.ring_mlo[slot], M.u.c.ring_mhi[slot]);
+      }
+      head += n;
+      visits += n;
+      if (visits > n_inner) { if (err) *err = 2; return -2; }
+      vf4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0}, c = {0, 0, 0, 0}, d = {0, 0, 0, 0};
+      if (lane < n) {
+        const vf4 *np = reinterpret_cast<const vf4 *>(s.nodes) + 4 * id;
+        a = np[0]; b = np[1]; c = np[2]; d = np[3];
+      }
+      const int cl = lane < n ? __float_as_int(a.w) : kNoChild;
+      const int cr = lane < n ? __float_as_int(b.w) : kNoChild;
+      const bool bad = lane < n && ((cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
+                                    (cr != kNoChild && (cr >= 0 ? cr >= n_inner : ~cr >= n_active)));
+      if (ballot(bad)) { if (err) *err = 3; return -2; }
+      uint64_t mL = 0, mR = 0;
+      for (uint64_t rem = rays; rem; rem &= rem - 1) {
+        const int r = __builtin_ctzll(rem);
+        const Ray q = lds_ray(M, self, r);
+        const float lo = M.rlo[r], hi = M.rhi[r];
+        if ((mk >> r) & 1) {
+          if (box_hit(a.x, a.y, a.z, b.x, b.y, b.z, q, lo, hi)) mL |= 1ull << r;
+          if (cr != kNoChild && box_hit(c.x, c.y, c.z, d.x, d.y, d.z, q, lo, hi)) mR |= 1ull << r;
+        }
+      }
+      // children, in lane order, left before right
+      const bool lI = mL != 0 && cl >= 0, rI = mR != 0 && cr >= 0 && cr != kNoChild;
+      const bool lL = mL != 0 && cl < 0 && cl != kNoChild, rL = mR != 0 && cr < 0 && cr != kNoChild;
+      {
+        const uint64_t b1 = ballot(lI || rI), b2 = ballot(lI && rI);
+        const int tot = __popcll(b1) + __popcll(b2);
+        if (tail + tot - head > kRingCap) return -1;
+        int pos = tail + __popcll(b1 & below) + __popcll(b2 & below);
+        if (lI) {
+          const int slot = pos & (kRingCap - 1);
+          M.u.c.ring_id[slot] = cl; M.u.c.ring_mlo[slot] = (uint32_t)mL; M.u.c.ring_mhi[slot] = (uint32_t)(mL >> 32);
+          pos++;
+        }
+        if (rI) {
+          const int slot = pos & (kRingCap - 1);
+          M.u.c.ring_id[slot] = cr; M.u.c.ring_mlo[slot] = (uint32_t)mR; M.u.c.ring_mhi[slot] = (uint32_t)(mR >> 32);
+        }
+        tail += tot;
+      }
+      {
+        const uint64_t b1 = ballot(lL || rL), b2 = ballot(lL && rL);
+        const int tot = __popcll(b1) + __popcll(b2);
+        if (staged + tot > kStageCap) return -1;
+        int pos = staged + __popcll(b1 & below) + __popcll(b2 & below);
+        if (lL) { M.u.c.st_id[pos] = ~cl; M.u.c.st_mlo[pos] = (uint32_t)mL; M.u.c.st_mhi[pos] = (uint32_t)(mL >> 32); pos++; }
+        if (rL) { M.u.c.st_id[pos] = ~cr; M.u.c.st_mlo[pos] = (uint32_t)mR; M.u.c.st_mhi[pos] = (uint32_t)(mR >> 32); }
+        staged += tot;
+      }
+    }
+    const bool done = head == tail;
+    // chord tests of staged leaves, 64 at a time, in staging order
+    while (staged >= 64 || (done && staged > 0)) {
+      __builtin_amdgcn_wave_barrier();
+      const int k = min(64, staged);
+      int j = 0;
+      uint64_t mk = 0;
+      if (lane < k) { j = M.u.c.st_id[lane]; mk = join64(M.u.c.st_mlo[lane], M.u.c.st_mhi[lane]); }
+      uint64_t hitm = 0;
+      float tmin = kInf, tmax = -kInf;
+      if (lane < k) {
+        const Gauss g = load_gauss_lane(s.geom, j);
+        for (uint64_t rem = mk; rem; rem &= rem - 1) {
+          const int r = __builtin_ctzll(rem);
+          const Ray q = lds_ray(M, self, r);
+          const float lo = M.rlo[r], hi = M.rhi[r];
+          const Chord ch = chord(g, q);
+          if (ch.exists && ch.tin <= hi && ch.tout >= lo) {
+            hitm |= 1ull << r;
+            tmin = fminf(tmin, ch.tin);
+            tmax = fmaxf(tmax, ch.tout);
+          } else if (stats) {
+            atomicAdd(&M.cnt_box[r], 1);
+          }
+        }
+      }
+      leaves_out += k;
+      const bool keep = hitm != 0;
+      const uint64_t bk = ballot(keep);
+      const int tot = __popcll(bk);
+      if (count + tot > kListCap) return -1;
+      if (keep) {
+        const int pos = count + __popcll(bk & below);
+        M.l_id[pos] = j;
+        M.l_mlo[pos] = (uint32_t)hitm;
+        M.l_mhi[pos] = (uint32_t)(hitm >> 32);
+        M.l_tin[pos] = tmin;
+        M.l_tout[pos] = tmax;
+      }
+      count += tot;
+      // move the remaining staged entries to the front
+      const int rest = staged - k;
+      int rid[2];
+      uint32_t rlo2[2], rhi2[2];
+      for (int e = 0; e < 2; e++) {
+        const int src = k + lane + 64 * e;
+        if (lane + 64 * e < rest) { rid[e] = M.u.c.st_id[src]; rlo2[e] = M.u.c.st_mlo[src]; rhi2[e] = M.u.c.st_mhi[src]; }
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int e = 0; e < 2; e++) {
+        const int dst = lane + 64 * e;
+        if (dst < rest) { M.u.c.st_id[dst] = rid[e]; M.u.c.st_mlo[dst] = rlo2[e]; M.u.c.st_mhi[dst] = rhi2[e]; }
+      }
+      staged = rest;
+    }
+    if (done && staged == 0) break;
+  }
+  nodes_out += visits;
+  sort_list(M, lane, count);
+  return count;
+}
+
+// ---------------------------------------------------------------------------
+// Sources of a segment's candidate Gaussians, all in Z-index order:
+// the window list (LDS), every active Gaussian (brute force) or, when a
+// window cannot fit even one segment, a depth-first traversal.
+
+enum SourceKind { SRC_LIST = 0, SRC_BRUTE = 1, SRC_DFS = 2 };
+
+// Calls fn(j, lane_may_hit) for every candidate; lane_may_hit is false for
+// lanes the candidate cannot touch (list mask).  `a_min`/`b_max` bound the
+// live lanes' segments for the list's uniform pre-check.
+template <class Fn>
+__device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, const WaveMem &M,
+                                                   int count, int lane, float a_min, float b_max,
+                                                   int n_active, const Ray &r, float lo, float hi,
+                                                   int32_t *err, Fn &&fn) {
+  if (kind == SRC_LIST) {
+    for (int e = 0; e < count; e++) {
+      const int o = uniform_int((int)(uint32_t)M.u.order[e]);
+      const float tin = M.l_tin[o], tout = M.l_tout[o];
+      if (uniform_float(tin) > b_max || uniform_float(tout) < a_min) continue;
+      const uint64_t mk = join64((uint32_t)uniform_int((int)M.l_mlo[o]),
+                                 (uint32_t)uniform_int((int)M.l_mhi[o]));
+      fn(uniform_int(M.l_id[o]), ((mk >> lane) & 1) != 0);
+    }
+  } else if (kind == SRC_BRUTE) {
+    for (int e = 0; e < n_active; e++) fn(e, true);
+  } else {
+    LeafIter it;
+    it.init(n_active, false);
+    for (int j; (j = it.next(s, r, lo, hi, err)) >= 0;) fn(j, true);
+  }
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return uniform_float(v);
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return uniform_float(v);
+}
+
+// Per-wave window bookkeeping shared by forward and backward.
+struct Window {
+  float len, len_min, len_max;   // uniform window length and its bounds
+  bool valid;                    // per lane: the current list covers this lane
+  float hi;                      // per lane window end
+  int count;                     // uniform list size
+  int kind;                      // SourceKind of the current candidates
+};
+
+// Makes sure every live lane whose segment fits its window can march; when
+// no live lane can, collects a new window for all live lanes.
+__device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts &op, WaveMem &M,
+                                              const Ray &r, int lane, int n_active, bool alive,
+                                              float a, float b, Window &w, bool stats,
+                                              int32_t *err, int32_t &nodes, int32_t &leaves,
+                                              bool &fits) {
+  if (op.brute_force) {
+    w.kind = SRC_BRUTE;
+    fits = alive;
+    return;
+  }
+  fits = alive && w.valid && b <= w.hi;
+  if (ballot(fits) != 0 || ballot(alive) == 0) return;
+  const uint64_t rays = ballot(alive);
+  for (;;) {
+    float lo = kInf, hi = -kInf;
+    if (alive) {
+      lo = a;
+      hi = fmaxf(a + w.len, b);
+    }
+    M.rlo[lane] = lo;
+    M.rhi[lane] = hi;
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = collect_window(s, M, r, lane, rays, n_active, stats, err, nodes, leaves);
+    if (cnt >= 0) {
+      w.count = cnt;
+      w.kind = SRC_LIST;
+      w.valid = alive;
+      w.hi = hi;
+      if (cnt < kListCap / 4) w.len = fminf(w.len * 1.5f, w.len_max);
+      break;
+    }
+    if (cnt == -2 || w.len <= w.len_min) {
+      // no window fits: this segment takes the depth-first path
+      w.kind = SRC_DFS;
+      w.valid = false;
+      break;
+    }
+    w.len = fmaxf(w.len * 0.5f, w.len_min);
+  }
+  fits = alive;
 }
 
 // ---------------------------------------------------------------------------
 // Forward kernel (and the hit-dump variant).
 
 template <int NS, bool DUMP>
-__global__ __launch_bounds__(kBlock) void k_forward(SceneDev s, ViewTable vt, MarchOpts op,
-                                                    FwdOut out, LaunchShape ls) {
-  const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
+__global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, MarchOpts op,
+                                                   FwdOut out, LaunchShape ls) {
+  __shared__ WaveMem M;
+  const int lane = threadIdx.x;
   const int n_active = uniform_int(s.counters[0]);
   const bool grid = !op.adaptive && op.ess != 2;
   const bool stats = out.stats != nullptr;
@@ -327,25 +766,29 @@ __global__ __launch_bounds__(kBlock) void k_forward(SceneDev s, ViewTable vt, Ma
       if (w < 0) break;
     } else {
       if (!first) break;
-      w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wib;
+      w = xcd_block(blockIdx.x, gridDim.x);
       if (w >= vt.n_tiles) break;
     }
     first = false;
 
     Pixel px;
-    View V;
     int dump_slot = 0;
     if (DUMP) {
-      V = vt.v[0];
       dump_slot = w * 64 + lane;
+      px.view = 0;
       px.valid = dump_slot < out.dump_n;
       const int pix = px.valid ? out.dump_pix[dump_slot] : 0;
-      px.px = pix % V.width; px.py = pix / V.width; px.ray = dump_slot;
+      px.px = pix % vt.v[0].width;
+      px.py = pix / vt.v[0].width;
+      px.ray = dump_slot;
     } else {
       px = tile_pixel(vt, op, w, lane);
-      V = vt.v[px.view];
     }
+    const View &V = vt.v[px.view];
     const Ray r = make_ray(V, px.px, px.py);
+    M.rdx[lane] = r.dx; M.rdy[lane] = r.dy; M.rdz[lane] = r.dz;
+    M.rix[lane] = r.ix; M.riy[lane] = r.iy; M.riz[lane] = r.iz;
+    M.cnt_box[lane] = 0;
     const float tn = V.t_near, tf = V.t_far;
     float Y[16];
     sh_basis(op.sh_k, r.dx, r.dy, r.dz, Y);
@@ -357,8 +800,16 @@ __global__ __launch_bounds__(kBlock) void k_forward(SceneDev s, ViewTable vt, Ma
     ss.a = tn;
     ss.cl_lo = tn;
     const float dS = op.dt * (float)NS;
+    Window win;
+    win.len_min = (float)NS * (op.adaptive ? op.dt_max : op.dt) * 1.0001f + 1e-6f;
+    win.len = (float)op.window_segments * win.len_min;
+    win.len_max = fmaxf(8.0f * win.len_min, 2.0f * win.len);
+    win.valid = false;
+    win.hi = -kInf;
+    win.count = 0;
+    win.kind = SRC_LIST;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    int32_t cnt[kNStatUsed] = {0, 0, 0, 0, 0, 0};
+    int32_t cnt[kNStatUsed] = {0, 0, 0, 0, 0, 0, 0, 0};
     float prev_a = -kInf, prev_b = -kInf;
     int n_dump = 0;
 
@@ -366,41 +817,39 @@ __global__ __launch_bounds__(kBlock) void k_forward(SceneDev s, ViewTable vt, Ma
       if (op.ess)
         closest_pass(s, op, n_active, r, tn, tf, dS, ss, ls.error_flag,
                      stats ? &cnt[ST_CLOSEST] : nullptr);
-      float a = 0.0f, b = 0.0f, dt = op.dt;
       if (ss.alive) {
-        a = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
-        if (!(a < tf) || !(T > op.t_eps)) ss.alive = false;
+        const float a0 = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
+        if (!(a0 < tf) || !(T > op.t_eps)) ss.alive = false;
       }
       if (ballot(ss.alive) == 0) break;
-      float lo = kInf, hi = -kInf;
+      float a = 0.0f, b = 0.0f, dt = op.dt, ts[NS];
       if (ss.alive) {
-        if (op.adaptive) dt = adaptive_dt(op, a, T);
-        b = grid ? fmaf((float)((ss.seg_i + 1) * NS), op.dt, tn) : fmaf((float)NS, dt, a);
-        lo = a;
-        hi = b;
-        if (!(b > a)) {   // no progress possible in FP32: stop this ray
+        if (!segment<NS>(op, grid, ss, tn, T, a, b, dt, ts)) {   // no progress in FP32
           ss.alive = false;
-          lo = kInf;
-          hi = -kInf;
           if (ls.error_flag) *ls.error_flag = 4;
         }
       }
-      float ts[NS];
-      sample_positions<NS>(grid, ss.seg_i, a, dt, tn, ts);
+      if (!ss.alive) {
+#pragma unroll
+        for (int k = 0; k < NS; k++) ts[k] = 0.0f;
+      }
+      bool go;
+      ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
+                    cnt[ST_NODES], cnt[ST_LEAVES], go);
+      const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
+      const float lo = go ? a : kInf, hi = go ? b : -kInf;
       float sg[NS], W0[NS], W1[NS], W2[NS];
 #pragma unroll
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
       int nhit = 0;
 
-      for_each_candidate(s, op, n_active, r, lo, hi, ls.error_flag, [&](int j) {
+      for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, lo, hi,
+                         ls.error_flag, [&](int j, bool may) {
+        const bool want = go && may;
+        if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
-        const bool hit = c.exists && c.tin <= hi && c.tout >= lo;
-        if (stats) {
-          const float *bx = s.aabb + 6 * (size_t)j;
-          const bool boxed = box_hit(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, lo, hi);
-          if (boxed && !hit) cnt[ST_BOX_ONLY]++;
-        }
+        const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
         if (ballot(hit) == 0) return;
         if (hit) {
           nhit++;
@@ -414,26 +863,35 @@ __global__ __launch_bounds__(kBlock) void k_forward(SceneDev s, ViewTable vt, Ma
           }
           float cr, cg, cb;
           colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
+          float wk[NS];
+          sample_weights<NS>(g, c, ts, wk);
 #pragma unroll
           for (int k = 0; k < NS; k++) {
-            const float u = ts[k] - c.ts;
-            const float q = fmaf(c.A * u, u, c.h2);
-            const float wv = exp2f(fmaf(-q, kHalfLog2e, g.l2sig));
-            const float w = q <= g.k2 ? wv : 0.0f;
-            sg[k] += w;
-            W0[k] = fmaf(w, cr, W0[k]);
-            W1[k] = fmaf(w, cg, W1[k]);
-            W2[k] = fmaf(w, cb, W2[k]);
+            sg[k] += wk[k];
+            W0[k] = fmaf(wk[k], cr, W0[k]);
+            W1[k] = fmaf(wk[k], cg, W1[k]);
+            W2[k] = fmaf(wk[k], cb, W2[k]);
           }
         }
       });
 
-      if (ss.alive) {
-        if (nhit == 0) {
-          if (op.ess) { ss.pending = true; ss.cl_lo = b; ss.seg_i += 1; }
-          else if (grid) ss.seg_i += 1;
-          else ss.a = b;
-        } else {
+      // an empty segment restarts at the next closest hit: inside the window
+      // from the list, otherwise through a closest-hit traversal
+      const bool empty = go && nhit == 0;
+      float best = kInf;
+      if (op.ess && win.kind == SRC_LIST && ballot(empty)) {
+        const float bmin = wave_min(empty ? b : kInf);
+        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r, lo, hi,
+                           ls.error_flag, [&](int j, bool may) {
+          const bool want = empty && may;
+          if (ballot(want) == 0) return;
+          const Gauss g = load_gauss(s.geom, j);
+          const Chord c = chord(g, r);
+          if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
+        });
+      }
+      if (go) {
+        if (nhit > 0) {
           if (stats) { cnt[ST_SEGMENTS]++; cnt[ST_P] += nhit; }
 #pragma unroll
           for (int k = 0; k < NS; k++) {
@@ -441,23 +899,23 @@ __global__ __launch_bounds__(kBlock) void k_forward(SceneDev s, ViewTable vt, Ma
               if (stats) cnt[ST_SAMPLES]++;
               if (sg[k] > 0.0f) {
                 const float x = sg[k] * dt;
-                const float alpha = one_minus_exp_neg(x);
-                const float f = T * (alpha / sg[k]);
+                const float f = T * (one_minus_exp_neg(x) * __builtin_amdgcn_rcpf(sg[k]));
                 C0 = fmaf(f, W0[k], C0);
                 C1 = fmaf(f, W1[k], C1);
                 C2 = fmaf(f, W2[k], C2);
-                T *= __expf(-x);
+                T *= exp_neg(x);
               }
             }
           }
           prev_a = a;
           prev_b = b;
-          if (grid) ss.seg_i += 1;
-          else ss.a = b;
         }
+        step_after(op, grid, nhit > 0, best, tn, dS, b, ss);
       }
+      if (win.kind == SRC_DFS) win.kind = SRC_LIST;
     }
 
+    if (stats) cnt[ST_BOX_ONLY] += M.cnt_box[lane];
     if (DUMP) {
       if (px.valid) out.dump_count[dump_slot] = n_dump;
     } else if (px.valid) {
@@ -473,32 +931,17 @@ __global__ __launch_bounds__(kBlock) void k_forward(SceneDev s, ViewTable vt, Ma
 }
 
 // ---------------------------------------------------------------------------
-// Backward kernel.
-
-// Reduce-scatter of 64 values across the wave: afterwards lane L holds the sum
-// over all lanes of v[L].
-__device__ __forceinline__ float wave_reduce_scatter64(float *v, int lane) {
-#pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) {
-    const bool up = (lane & h) != 0;
-#pragma unroll
-    for (int i = 0; i < h; i++) {
-      const float keep = up ? v[i + h] : v[i];
-      const float send = up ? v[i] : v[i + h];
-      v[i] = keep + __shfl_xor(send, h, 64);
-    }
-  }
-  return v[0];
-}
-
-constexpr int kListCap = 512;   // per-wave LDS list of a segment's Gaussians
+// Backward kernel: replays the forward's segments from the same window lists
+// (or brute force / depth-first sources) in the same order, recomputes the
+// transmittance before every sample, derives dL/dsigma_k and dL/dW_k, then
+// revisits the segment's Gaussians for their parameter adjoints, reduced over
+// the wave before one atomic per accumulator slot.
 
 template <int NS>
-__global__ __launch_bounds__(kBlock) void k_backward(SceneDev s, ViewTable vt, MarchOpts op,
-                                                     BwdIn in, LaunchShape ls) {
-  __shared__ int32_t list_mem[kWavesPerBlock][kListCap];
-  const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
-  int32_t *list = list_mem[wib];
+__global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, MarchOpts op,
+                                                    BwdIn in, LaunchShape ls) {
+  __shared__ WaveMem M;
+  const int lane = threadIdx.x;
   const int n_active = uniform_int(s.counters[0]);
   const bool grid = !op.adaptive && op.ess != 2;
   bool first = true;
@@ -509,7 +952,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(SceneDev s, ViewTable vt, M
       if (w < 0) break;
     } else {
       if (!first) break;
-      w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wib;
+      w = xcd_block(blockIdx.x, gridDim.x);
       if (w >= vt.n_tiles) break;
     }
     first = false;
@@ -517,22 +960,22 @@ __global__ __launch_bounds__(kBlock) void k_backward(SceneDev s, ViewTable vt, M
     const Pixel px = tile_pixel(vt, op, w, lane);
     const View &V = vt.v[px.view];
     const Ray r = make_ray(V, px.px, px.py);
+    M.rdx[lane] = r.dx; M.rdy[lane] = r.dy; M.rdz[lane] = r.dz;
+    M.rix[lane] = r.ix; M.riy[lane] = r.iy; M.riz[lane] = r.iz;
     const float tn = V.t_near, tf = V.t_far;
     float Y[16];
     sh_basis(op.sh_k, r.dx, r.dy, r.dz, Y);
-    float Gc0 = 0, Gc1 = 0, Gc2 = 0, Cf0 = 0, Cf1 = 0, Cf2 = 0, gT = 0, Tfin = 0;
+    float Gc0 = 0, Gc1 = 0, Gc2 = 0, GCf = 0;
     if (px.valid) {
-      Gc0 = in.grad_rgb[3 * (size_t)px.ray];
-      Gc1 = in.grad_rgb[3 * (size_t)px.ray + 1];
-      Gc2 = in.grad_rgb[3 * (size_t)px.ray + 2];
-      Cf0 = in.rgb[3 * (size_t)px.ray];
-      Cf1 = in.rgb[3 * (size_t)px.ray + 1];
-      Cf2 = in.rgb[3 * (size_t)px.ray + 2];
-      Tfin = in.T[px.ray];
-      gT = in.grad_T ? in.grad_T[px.ray] : 0.0f;
+      const size_t q = 3 * (size_t)px.ray;
+      Gc0 = in.grad_rgb[q];
+      Gc1 = in.grad_rgb[q + 1];
+      Gc2 = in.grad_rgb[q + 2];
+      const float gT = in.grad_T ? in.grad_T[px.ray] : 0.0f;
+      // G . C_fin + g_T T_fin; the colour still to come behind sample k is
+      // C_fin - (prefix through k), kept as the running scalar GP = G . prefix
+      GCf = Gc0 * in.rgb[q] + Gc1 * in.rgb[q + 1] + Gc2 * in.rgb[q + 2] + gT * in.T[px.ray];
     }
-    // G . (C_fin - P_k) + g_T T_fin, kept as a running scalar: GC - G.P
-    const float GCf = Gc0 * Cf0 + Gc1 * Cf1 + Gc2 * Cf2 + gT * Tfin;
     float GP = 0.0f;
     SegState ss;
     ss.alive = px.valid;
@@ -541,80 +984,86 @@ __global__ __launch_bounds__(kBlock) void k_backward(SceneDev s, ViewTable vt, M
     ss.a = tn;
     ss.cl_lo = tn;
     const float dS = op.dt * (float)NS;
+    Window win;
+    win.len_min = (float)NS * (op.adaptive ? op.dt_max : op.dt) * 1.0001f + 1e-6f;
+    win.len = (float)op.window_segments * win.len_min;
+    win.len_max = fmaxf(8.0f * win.len_min, 2.0f * win.len);
+    win.valid = false;
+    win.hi = -kInf;
+    win.count = 0;
+    win.kind = SRC_LIST;
+    int32_t dummy_nodes = 0, dummy_leaves = 0;
     float T = 1.0f;
 
     for (;;) {
       if (op.ess) closest_pass(s, op, n_active, r, tn, tf, dS, ss, ls.error_flag, nullptr);
-      float a = 0.0f, b = 0.0f, dt = op.dt;
       if (ss.alive) {
-        a = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
-        if (!(a < tf) || !(T > op.t_eps)) ss.alive = false;
+        const float a0 = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
+        if (!(a0 < tf) || !(T > op.t_eps)) ss.alive = false;
       }
       if (ballot(ss.alive) == 0) break;
-      float lo = kInf, hi = -kInf;
+      float a = 0.0f, b = 0.0f, dt = op.dt, ts[NS];
       if (ss.alive) {
-        if (op.adaptive) dt = adaptive_dt(op, a, T);
-        b = grid ? fmaf((float)((ss.seg_i + 1) * NS), op.dt, tn) : fmaf((float)NS, dt, a);
-        lo = a;
-        hi = b;
-        if (!(b > a)) {   // no progress possible in FP32: stop this ray
+        if (!segment<NS>(op, grid, ss, tn, T, a, b, dt, ts)) {
           ss.alive = false;
-          lo = kInf;
-          hi = -kInf;
           if (ls.error_flag) *ls.error_flag = 4;
         }
       }
-      float ts[NS];
-      sample_positions<NS>(grid, ss.seg_i, a, dt, tn, ts);
+      if (!ss.alive) {
+#pragma unroll
+        for (int k = 0; k < NS; k++) ts[k] = 0.0f;
+      }
+      bool go;
+      ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, false, ls.error_flag,
+                    dummy_nodes, dummy_leaves, go);
+      const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
+      const float lo = go ? a : kInf, hi = go ? b : -kInf;
       float sg[NS], W0[NS], W1[NS], W2[NS];
 #pragma unroll
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
       int nhit = 0;
-      int nlist = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
-      for_each_candidate(s, op, n_active, r, lo, hi, ls.error_flag, [&](int j) {
+      for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, lo, hi,
+                         ls.error_flag, [&](int j, bool may) {
+        const bool want = go && may;
+        if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
-        const bool hit = c.exists && c.tin <= hi && c.tout >= lo;
+        const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
         if (ballot(hit) == 0) return;
-        if (nlist < kListCap && lane == 0) list[nlist] = j;
-        nlist++;
         if (hit) {
           nhit++;
           float cr, cg, cb;
           colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
+          float wk[NS];
+          sample_weights<NS>(g, c, ts, wk);
 #pragma unroll
           for (int k = 0; k < NS; k++) {
-            const float u = ts[k] - c.ts;
-            const float q = fmaf(c.A * u, u, c.h2);
-            const float wv = exp2f(fmaf(-q, kHalfLog2e, g.l2sig));
-            const float w = q <= g.k2 ? wv : 0.0f;
-            sg[k] += w;
-            W0[k] = fmaf(w, cr, W0[k]);
-            W1[k] = fmaf(w, cg, W1[k]);
-            W2[k] = fmaf(w, cb, W2[k]);
+            sg[k] += wk[k];
+            W0[k] = fmaf(wk[k], cr, W0[k]);
+            W1[k] = fmaf(wk[k], cg, W1[k]);
+            W2[k] = fmaf(wk[k], cb, W2[k]);
           }
         }
       });
 
-      __builtin_amdgcn_wave_barrier();
-      // per-sample adjoints dL/dsigma_k (reusing sg) and dL/dW_k (reusing W)
-      bool any = false;
-      if (ss.alive && nhit > 0) {
-        any = true;
+      // per-sample adjoints: dL/dsigma_k (into sg) and dL/dW_k (into W)
+      const bool any = go && nhit > 0;
+      if (any) {
 #pragma unroll
         for (int k = 0; k < NS; k++) {
           float dsig = 0.0f, dW = 0.0f;
           if (ts[k] < tf && sg[k] > 0.0f) {
             const float x = sg[k] * dt;
-            const float E = __expf(-x);
+            const float E = exp_neg(x);
+            const float rs = __builtin_amdgcn_rcpf(sg[k]);
             const float alpha = one_minus_exp_neg(x);
-            const float phi = alpha / sg[k];
+            const float phi = alpha * rs;
             // d(alpha/sigma)/dsigma = dt^2 f'(x), f(x) = (1 - e^-x)/x
             const float dphi = x < 1e-2f
                 ? dt * dt * (-0.5f + x * (1.0f / 3.0f - x * (0.125f - x * (1.0f / 30.0f))))
-                : (x * E - alpha) / (sg[k] * sg[k]);
+                : (x * E - alpha) * rs * rs;
             const float GW = Gc0 * W0[k] + Gc1 * W1[k] + Gc2 * W2[k];
             GP = fmaf(T * phi, GW, GP);
             dsig = T * dphi * GW - dt * (GCf - GP);
@@ -628,91 +1077,86 @@ __global__ __launch_bounds__(kBlock) void k_backward(SceneDev s, ViewTable vt, M
         }
       }
 
-      // pass B: per-Gaussian gradient contributions, wave-reduced, then atomics
+      // pass B: per-Gaussian adjoints, wave-reduced, one atomic per slot
       if (ballot(any) != 0) {
-        const int nl = nlist;
-        auto leafB = [&](int j) {
+        for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, lo, hi,
+                           ls.error_flag, [&](int j, bool may) {
+          const bool want = any && may;
+          if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
           float opx, opy, opz, dpx, dpy, dpz;
           ray_local(g, r, opx, opy, opz, dpx, dpy, dpz);
           const Chord c = chord(g, r);
-          const bool hit = any && c.exists && c.tin <= hi && c.tout >= lo;
+          const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
           if (ballot(hit) == 0) return;
-          float v[kAccFloats];
+          float D0 = 0.0f, D1 = 0.0f, D2 = 0.0f, dc0 = 0.0f, dc1 = 0.0f, dc2 = 0.0f, ds = 0.0f;
+          float v[16];
 #pragma unroll
-          for (int e = 0; e < kAccFloats; e++) v[e] = 0.0f;
+          for (int e2 = 0; e2 < 16; e2++) v[e2] = 0.0f;
           if (hit) {
             float cr, cg, cb;
             colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
-            float D0 = 0.0f, D1 = 0.0f, D2 = 0.0f, dc0 = 0.0f, dc1 = 0.0f, dc2 = 0.0f, ds = 0.0f;
+            float wk[NS];
+            sample_weights<NS>(g, c, ts, wk);
 #pragma unroll
             for (int k = 0; k < NS; k++) {
               const float u = ts[k] - c.ts;
-              const float q = fmaf(c.A * u, u, c.h2);
-              const float wv = exp2f(fmaf(-q, kHalfLog2e, g.l2sig));
-              const float w = q <= g.k2 ? wv : 0.0f;
               const float dw = sg[k] + W0[k] * cr + W1[k] * cg + W2[k] * cb;
-              const float wdw = w * dw;
+              const float wdw = wk[k] * dw;
               ds += wdw;
               const float dq = -0.5f * wdw;
               D0 += dq;
               D1 = fmaf(dq, u, D1);
               D2 = fmaf(dq * u, u, D2);
-              dc0 = fmaf(w, W0[k], dc0);
-              dc1 = fmaf(w, W1[k], dc1);
-              dc2 = fmaf(w, W2[k], dc2);
+              dc0 = fmaf(wk[k], W0[k], dc0);
+              dc1 = fmaf(wk[k], W1[k], dc1);
+              dc2 = fmaf(wk[k], W2[k], dc2);
             }
             // z_k = p + u_k d' with p = o' + t* d' (closest approach, local frame)
             const float pxl = fmaf(c.ts, dpx, opx), pyl = fmaf(c.ts, dpy, opy),
                         pzl = fmaf(c.ts, dpz, opz);
-            const float Z0 = fmaf(D0, pxl, D1 * dpx), Z1 = fmaf(D0, pyl, D1 * dpy),
-                        Z2 = fmaf(D0, pzl, D1 * dpz);
-            const float U0 = fmaf(D1, pxl, D2 * dpx), U1 = fmaf(D1, pyl, D2 * dpy),
-                        U2 = fmaf(D1, pzl, D2 * dpz);
+            const float Zs[3] = {fmaf(D0, pxl, D1 * dpx), fmaf(D0, pyl, D1 * dpy),
+                                 fmaf(D0, pzl, D1 * dpz)};
+            const float Us[3] = {fmaf(D1, pxl, D2 * dpx), fmaf(D1, pyl, D2 * dpy),
+                                 fmaf(D1, pzl, D2 * dpz)};
             // world offset of the closest-approach point from the mean
-            const float P0 = fmaf(c.ts, r.dx, r.ox - g.mx), P1 = fmaf(c.ts, r.dy, r.oy - g.my),
-                        P2 = fmaf(c.ts, r.dz, r.oz - g.mz);
-            v[0] = Z0; v[1] = Z1; v[2] = Z2;
-            const float Zs[3] = {Z0, Z1, Z2}, Us[3] = {U0, U1, U2}, Ps[3] = {P0, P1, P2},
-                        ds3[3] = {r.dx, r.dy, r.dz};
+            const float Ps[3] = {fmaf(c.ts, r.dx, r.ox - g.mx), fmaf(c.ts, r.dy, r.oy - g.my),
+                                 fmaf(c.ts, r.dz, r.oz - g.mz)};
+            const float dd[3] = {r.dx, r.dy, r.dz};
+            v[0] = Zs[0]; v[1] = Zs[1]; v[2] = Zs[2];
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
-              for (int jj = 0; jj < 3; jj++) v[3 + 3 * i + jj] = fmaf(Zs[i], Ps[jj], Us[i] * ds3[jj]);
+              for (int jj = 0; jj < 3; jj++) v[3 + 3 * i + jj] = fmaf(Zs[i], Ps[jj], Us[i] * dd[jj]);
             v[12] = fmaf(D0, pxl * pxl, fmaf(2.0f * D1, pxl * dpx, D2 * dpx * dpx));
             v[13] = fmaf(D0, pyl * pyl, fmaf(2.0f * D1, pyl * dpy, D2 * dpy * dpy));
             v[14] = fmaf(D0, pzl * pzl, fmaf(2.0f * D1, pzl * dpz, D2 * dpz * dpz));
-            v[15] = ds / g.sig;
-#pragma unroll
-            for (int m = 0; m < 16; m++) {
-              if (m < op.sh_k) {
-                v[16 + 3 * m] = Y[m] * dc0;
-                v[17 + 3 * m] = Y[m] * dc1;
-                v[18 + 3 * m] = Y[m] * dc2;
-              }
-            }
+            v[15] = ds * __builtin_amdgcn_rcpf(g.sig);
           }
-          const float tot = wave_reduce_scatter64(v, lane);
-          if (lane < 16 + 3 * op.sh_k)
-            unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + lane, tot);
-        };
-        if (nl <= kListCap) {
-          for (int e = 0; e < nl; e++) leafB(uniform_int(list[e]));
-        } else {
-          for_each_candidate(s, op, n_active, r, lo, hi, ls.error_flag, leafB);
-        }
+          // slots: [0,16) geometry and density, then 16 SH coefficients per channel
+          const float mine = wave_reduce_slots(v, Y, dc0, dc1, dc2, lane);
+          if (lane < 16 || (lane & 15) < op.sh_k)
+            unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + lane, mine);
+        });
       }
 
-      if (ss.alive) {
-        if (nhit == 0) {
-          if (op.ess) { ss.pending = true; ss.cl_lo = b; ss.seg_i += 1; }
-          else if (grid) ss.seg_i += 1;
-          else ss.a = b;
-        } else {
-          if (grid) ss.seg_i += 1;
-          else ss.a = b;
-        }
+      // restart after an empty segment: from the list inside the window, else
+      // through the closest-hit traversal (same decisions as the forward)
+      const bool empty = go && nhit == 0;
+      float best = kInf;
+      if (op.ess && win.kind == SRC_LIST && ballot(empty)) {
+        const float bmin = wave_min(empty ? b : kInf);
+        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r, lo, hi,
+                           ls.error_flag, [&](int j, bool may) {
+          const bool want = empty && may;
+          if (ballot(want) == 0) return;
+          const Gauss g = load_gauss(s.geom, j);
+          const Chord c = chord(g, r);
+          if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
+        });
       }
+      if (go) step_after(op, grid, nhit > 0, best, tn, dS, b, ss);
+      if (win.kind == SRC_DFS) win.kind = SRC_LIST;
     }
   }
 }
@@ -773,8 +1217,11 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t n, const int32_t *__re
   const float qh[4] = {w, x, y, z};
   for (int k = 0; k < 4; k++) gq[4 * u + k] = fmaf(keep, gq[4 * u + k], (dq[k] - pr * qh[k]) / qn);
   gd[u] = fmaf(keep, gd[u], A[15]);
-  for (int k = 0; k < 3 * sh_k; k++)
-    gsh[(size_t)3 * sh_k * u + k] = fmaf(keep, gsh[(size_t)3 * sh_k * u + k], A[16 + k]);
+  for (int m = 0; m < sh_k; m++)
+    for (int ch = 0; ch < 3; ch++) {
+      const size_t o = (size_t)3 * sh_k * u + 3 * m + ch;
+      gsh[o] = fmaf(keep, gsh[o], A[16 + 16 * ch + m]);
+    }
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -788,8 +1235,8 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 template <int NS>
 static void fwd_dispatch(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
                          const FwdOut &out, const LaunchShape &ls, hipStream_t st) {
-  if (out.dump_pix) k_forward<NS, true><<<ls.grid, kBlock, 0, st>>>(s, vt, op, out, ls);
-  else k_forward<NS, false><<<ls.grid, kBlock, 0, st>>>(s, vt, op, out, ls);
+  if (out.dump_pix) k_forward<NS, true><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
+  else k_forward<NS, false><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
 }
 
 hipError_t launch_forward(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
@@ -816,11 +1263,11 @@ hipError_t launch_backward(const SceneDev &s, const ViewTable &vt, const MarchOp
     if (e != hipSuccess) return e;
   }
   switch (op.n_s) {
-    case 1: k_backward<1><<<ls.grid, kBlock, 0, st>>>(s, vt, op, in, ls); break;
-    case 2: k_backward<2><<<ls.grid, kBlock, 0, st>>>(s, vt, op, in, ls); break;
-    case 4: k_backward<4><<<ls.grid, kBlock, 0, st>>>(s, vt, op, in, ls); break;
-    case 8: k_backward<8><<<ls.grid, kBlock, 0, st>>>(s, vt, op, in, ls); break;
-    case 16: k_backward<16><<<ls.grid, kBlock, 0, st>>>(s, vt, op, in, ls); break;
+    case 1: k_backward<1><<<ls.grid, kWave, 0, st>>>(s, vt, op, in, ls); break;
+    case 2: k_backward<2><<<ls.grid, kWave, 0, st>>>(s, vt, op, in, ls); break;
+    case 4: k_backward<4><<<ls.grid, kWave, 0, st>>>(s, vt, op, in, ls); break;
+    case 8: k_backward<8><<<ls.grid, kWave, 0, st>>>(s, vt, op, in, ls); break;
+    case 16: k_backward<16><<<ls.grid, kWave, 0, st>>>(s, vt, op, in, ls); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -11,11 +11,11 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librgx.so")
+LIB_PATH = os.environ.get("RGX_LIBRARY", os.path.join(HERE, "librgx.so"))
 
 RGX_OK = 0
 NSTAT = 8
-STAT_NAMES = ("Q", "P", "samples", "segments", "closest", "box_only")
+STAT_NAMES = ("Q", "P", "samples", "segments", "closest", "box_only", "nodes", "leaves")
 
 
 class RgxError(RuntimeError):
@@ -43,7 +43,8 @@ class RenderOpts(C.Structure):
                 ("dt_max", C.c_float), ("beta", C.c_float), ("n_s", C.c_int32),
                 ("t_eps", C.c_float), ("ess", C.c_int32), ("brute_force", C.c_int32),
                 ("ray_order", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("persistent", C.c_int32), ("bg", C.c_float * 3)]
+                ("persistent", C.c_int32), ("window_segments", C.c_int32),
+                ("bg", C.c_float * 3)]
 
 
 class Grads(C.Structure):
@@ -133,6 +134,7 @@ def make_opts(o) -> RenderOpts:
     r.ray_order = int(o.ray_order)
     r.tile_w, r.tile_h = int(o.tile_w), int(o.tile_h)
     r.persistent = int(bool(o.persistent))
+    r.window_segments = int(getattr(o, "window_segments", 0))
     for i in range(3):
         r.bg[i] = float(o.bg[i])
     return r

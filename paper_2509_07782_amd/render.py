@@ -30,6 +30,7 @@ class RenderOptions:
     tile_w: int = 8
     tile_h: int = 8
     persistent: bool = False
+    window_segments: int = 2
     bg: tuple = (0.0, 0.0, 0.0)
 
 
@@ -115,3 +116,49 @@ class RayMarchFunction(torch.autograd.Function):
 def render(params: dict, sh_degree: int, renderer: Renderer, cams, opts: RenderOptions):
     return RayMarchFunction.apply(params["means"], params["log_scales"], params["quats"],
                                   params["density"], params["sh"], renderer, cams, opts, sh_degree)
+
+
+class TrainStep:
+    """One training step of the ray marcher as a replayable HIP graph.
+
+    The step rebuilds the acceleration structure from the current parameter
+    values, renders every view in one batched launch, evaluates `loss_fn`
+    on (rgb, T), back-propagates through RayMarchFunction and applies
+    p -= lr * grad in place.  It is captured once (after warm-up calls that
+    size every buffer, so nothing is allocated inside the graph) and replayed
+    with a single launch per step.  All library work is kernels on the
+    capturing stream; accumulators and work queues are cleared by kernels,
+    never by memset nodes."""
+
+    def __init__(self, renderer: Renderer, params: dict, sh_degree: int, cams,
+                 opts: RenderOptions, loss_fn, lr: float = 0.0, warmup: int = 2):
+        self.renderer, self.params, self.deg = renderer, params, sh_degree
+        self.cams, self.opts, self.loss_fn, self.lr = cams, opts, loss_fn, lr
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self._step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.loss, self.rgb, self.T = self._step()
+        self.grads = {k: params[k].grad for k in PARAM_KEYS}
+
+    def _step(self):
+        for p in self.params.values():
+            p.grad = None
+        self.renderer.build(self.params, self.deg, force=True)
+        rgb, T = render(self.params, self.deg, self.renderer, self.cams, self.opts)
+        loss = self.loss_fn(rgb, T)
+        loss.backward()
+        if self.lr:
+            with torch.no_grad():
+                for p in self.params.values():
+                    p.add_(p.grad, alpha=-self.lr)
+        return loss.detach(), rgb.detach(), T.detach()
+
+    def replay(self):
+        self.graph.replay()
+        return self.loss
