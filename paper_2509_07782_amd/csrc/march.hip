@@ -441,7 +441,7 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
 
 constexpr int kRingCap = 256;    // frontier entries (power of two)
 constexpr int kStageCap = 192;   // staged leaves: < 64 left over + 128 per round
-constexpr int kListCap = 512;    // window list entries
+constexpr int kListCap = 256;    // window list entries (LDS budget: 3 waves per SIMD)
 
 struct WaveMem {
   float rdx[64], rdy[64], rdz[64], rix[64], riy[64], riz[64], rlo[64], rhi[64];
@@ -666,13 +666,26 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
                                                    int n_active, const Ray &r, float lo, float hi,
                                                    int32_t *err, Fn &&fn) {
   if (kind == SRC_LIST) {
-    for (int e = 0; e < count; e++) {
-      const int o = uniform_int((int)(uint32_t)M.u.order[e]);
-      const float tin = M.l_tin[o], tout = M.l_tout[o];
-      if (uniform_float(tin) > b_max || uniform_float(tout) < a_min) continue;
-      const uint64_t mk = join64((uint32_t)uniform_int((int)M.l_mlo[o]),
-                                 (uint32_t)uniform_int((int)M.l_mhi[o]));
-      fn(uniform_int(M.l_id[o]), ((mk >> lane) & 1) != 0);
+    // 64 entries at a time: lane i holds entry base + i; the depth pre-check
+    // is one ballot, and the surviving entries are read back with readlane
+    for (int base = 0; base < count; base += 64) {
+      const int e = base + lane;
+      int id = 0;
+      uint32_t mlo = 0, mhi = 0;
+      bool keep = false;
+      if (e < count) {
+        const int o = (int)(uint32_t)M.u.order[e];
+        keep = !(M.l_tin[o] > b_max) && !(M.l_tout[o] < a_min);
+        id = M.l_id[o];
+        mlo = M.l_mlo[o];
+        mhi = M.l_mhi[o];
+      }
+      for (uint64_t bits = ballot(keep); bits; bits &= bits - 1) {
+        const int src = __builtin_ctzll(bits);
+        const uint64_t mk = join64((uint32_t)__builtin_amdgcn_readlane((int)mlo, src),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)mhi, src));
+        fn(__builtin_amdgcn_readlane(id, src), ((mk >> lane) & 1) != 0);
+      }
     }
   } else if (kind == SRC_BRUTE) {
     for (int e = 0; e < n_active; e++) fn(e, true);
@@ -750,14 +763,14 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
 // ---------------------------------------------------------------------------
 // Forward kernel (and the hit-dump variant).
 
-template <int NS, bool DUMP>
+template <int NS, bool DUMP, bool STATS>
 __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, MarchOpts op,
                                                    FwdOut out, LaunchShape ls) {
   __shared__ WaveMem M;
   const int lane = threadIdx.x;
   const int n_active = uniform_int(s.counters[0]);
   const bool grid = !op.adaptive && op.ess != 2;
-  const bool stats = out.stats != nullptr;
+  constexpr bool stats = STATS;
   bool first = true;
   for (;;) {
     int w;
@@ -1176,12 +1189,13 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t n, const int32_t *__re
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t u = perm[i];
-  const float keep = accumulate ? 1.0f : 0.0f;
+  // overwrite mode never reads the output buffers (they may hold anything)
+  auto put = [accumulate](float &dst, float v) { dst = accumulate ? dst + v : v; };
   if (i >= counters[0]) {   // inactive Gaussian: zero gradient
-    for (int k = 0; k < 3; k++) { gm[3 * u + k] *= keep; gl[3 * u + k] *= keep; }
-    for (int k = 0; k < 4; k++) gq[4 * u + k] *= keep;
-    gd[u] *= keep;
-    for (int k = 0; k < 3 * sh_k; k++) gsh[(size_t)3 * sh_k * u + k] *= keep;
+    for (int k = 0; k < 3; k++) { put(gm[3 * u + k], 0.0f); put(gl[3 * u + k], 0.0f); }
+    for (int k = 0; k < 4; k++) put(gq[4 * u + k], 0.0f);
+    put(gd[u], 0.0f);
+    for (int k = 0; k < 3 * sh_k; k++) put(gsh[(size_t)3 * sh_k * u + k], 0.0f);
     return;
   }
   float A[kAccFloats];
@@ -1195,10 +1209,9 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t n, const int32_t *__re
   float Z[3] = {A[0], A[1], A[2]};
   // dL/dmu = -2 M^T Z
   for (int jj = 0; jj < 3; jj++)
-    gm[3 * u + jj] = fmaf(keep, gm[3 * u + jj],
-                          -2.0f * (G[G_M + jj] * Z[0] + G[G_M + 3 + jj] * Z[1] + G[G_M + 6 + jj] * Z[2]));
+    put(gm[3 * u + jj], -2.0f * (G[G_M + jj] * Z[0] + G[G_M + 3 + jj] * Z[1] + G[G_M + 6 + jj] * Z[2]));
   // dL/dl_i = -2 sum z_i^2 dq
-  for (int k = 0; k < 3; k++) gl[3 * u + k] = fmaf(keep, gl[3 * u + k], -2.0f * A[12 + k]);
+  for (int k = 0; k < 3; k++) put(gl[3 * u + k], -2.0f * A[12 + k]);
   // dL/dR_ji = 2 G'_ij / s_i
   const float *X = aux + (size_t)kAuxFloats * i;
   float dR[9];
@@ -1215,12 +1228,11 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t n, const int32_t *__re
                   y * dR[5] + x * dR[6] + y * dR[7]);
   const float pr = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
   const float qh[4] = {w, x, y, z};
-  for (int k = 0; k < 4; k++) gq[4 * u + k] = fmaf(keep, gq[4 * u + k], (dq[k] - pr * qh[k]) / qn);
-  gd[u] = fmaf(keep, gd[u], A[15]);
+  for (int k = 0; k < 4; k++) put(gq[4 * u + k], (dq[k] - pr * qh[k]) / qn);
+  put(gd[u], A[15]);
   for (int m = 0; m < sh_k; m++)
     for (int ch = 0; ch < 3; ch++) {
-      const size_t o = (size_t)3 * sh_k * u + 3 * m + ch;
-      gsh[o] = fmaf(keep, gsh[o], A[16 + 16 * ch + m]);
+      put(gsh[(size_t)3 * sh_k * u + 3 * m + ch], A[16 + 16 * ch + m]);
     }
 }
 
@@ -1235,8 +1247,9 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 template <int NS>
 static void fwd_dispatch(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
                          const FwdOut &out, const LaunchShape &ls, hipStream_t st) {
-  if (out.dump_pix) k_forward<NS, true><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
-  else k_forward<NS, false><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
+  if (out.dump_pix) k_forward<NS, true, false><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
+  else if (out.stats) k_forward<NS, false, true><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
+  else k_forward<NS, false, false><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
 }
 
 hipError_t launch_forward(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
