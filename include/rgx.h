@@ -119,7 +119,9 @@ enum {
   RGX_STAT_BOX_ONLY,     /* leaves whose AABB met the segment but whose ellipsoid did not */
   RGX_STAT_NODES,        /* BVH nodes loaded by the wave for the segment collections */
   RGX_STAT_LEAVES,       /* leaves the wave visited for the segment collections */
-  RGX_NSTAT = 8
+  RGX_STAT_WINDOWS,      /* window collections the wave made (attempts included) */
+  RGX_STAT_DFS,          /* segments whose candidates came from a depth-first traversal */
+  RGX_NSTAT = 10
 };
 
 /* Create / destroy a context on HIP device `device`.  rgx_create allocates. */
@@ -183,6 +185,24 @@ rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *bvh, uint64_t *keys, i
 /* Debug: device-side error flags of the context (synchronises the stream).
    flags[0] != 0 means a traversal exceeded its stack (results invalid). */
 rgx_status rgx_error_flags(rgx_context *ctx, int32_t *flags /*host*/, hipStream_t stream);
+
+/* Optional kernel timing, for measurement.  While enabled, every launch made
+   by rgx_build_bvh, rgx_render_forward and rgx_render_backward is bracketed
+   by two HIP events recorded on the caller's stream (so the interval is that
+   launch's duration on its own stream).  Do not enable it while a stream is
+   being captured into a graph.  Enabling or disabling clears the record. */
+enum {
+  RGX_KERN_BUILD = 0,    /* the whole build sequence of one rgx_build_bvh */
+  RGX_KERN_FORWARD,      /* one forward march launch (one per chunk of views) */
+  RGX_KERN_BACKWARD,     /* one backward march launch */
+  RGX_KERN_FINALIZE,     /* gradient chain rule + scatter to user order */
+  RGX_NKERN = 4
+};
+rgx_status rgx_set_kernel_timing(rgx_context *ctx, int32_t enable);
+/* Waits for the recorded events and returns, per RGX_KERN_* kind, the summed
+   milliseconds ms[RGX_NKERN] and the number of launches launches[RGX_NKERN]
+   (host arrays).  reset != 0 clears the record afterwards. */
+rgx_status rgx_kernel_times(rgx_context *ctx, double *ms, int64_t *launches, int32_t reset);
 
 const char *rgx_status_string(rgx_status s);
 const char *rgx_last_error(const rgx_context *ctx);

@@ -19,7 +19,8 @@ using namespace rgx;
 static_assert(RGX_STAT_Q == ST_Q && RGX_STAT_P == ST_P && RGX_STAT_SAMPLES == ST_SAMPLES &&
                   RGX_STAT_SEGMENTS == ST_SEGMENTS && RGX_STAT_CLOSEST == ST_CLOSEST &&
                   RGX_STAT_BOX_ONLY == ST_BOX_ONLY && RGX_STAT_NODES == ST_NODES &&
-                  RGX_STAT_LEAVES == ST_LEAVES && RGX_NSTAT == kNStat,
+                  RGX_STAT_LEAVES == ST_LEAVES && RGX_STAT_WINDOWS == ST_WINDOWS &&
+                  RGX_STAT_DFS == ST_DFS && RGX_NSTAT == kNStat,
               "stat slots");
 
 namespace {
@@ -37,7 +38,36 @@ struct rgx_context {
   std::string last_error;
   int32_t *queue = nullptr;        // 8 persistent-launch queues + error flag
   std::map<std::tuple<int, int, int, int>, int32_t *> tile_orders;
+  // optional per-launch timing: event pairs recorded on the caller's stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev;       // 2 per recorded launch, reused after a reset
+  std::vector<int> ev_kind;         // RGX_KERN_* of each recorded launch
+  size_t ev_used = 0;
 };
+
+// Records hipEvents on `stream` around `launch` when timing is enabled.
+template <class F>
+static hipError_t timed(rgx_context *ctx, int kind, hipStream_t stream, F &&launch) {
+  if (!ctx->timing) return launch();
+  if (ctx->ev_used + 2 > ctx->ev.size()) {
+    for (int k = 0; k < 2; k++) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ctx->ev.push_back(e);
+    }
+    ctx->ev_kind.resize(ctx->ev.size() / 2);
+  }
+  const size_t i = ctx->ev_used;
+  hipError_t r = hipEventRecord(ctx->ev[i], stream);
+  if (r == hipSuccess) r = launch();
+  if (r == hipSuccess) r = hipEventRecord(ctx->ev[i + 1], stream);
+  if (r == hipSuccess) {
+    ctx->ev_kind[i / 2] = kind;
+    ctx->ev_used += 2;
+  }
+  return r;
+}
 
 struct rgx_bvh {
   rgx_context *ctx = nullptr;
@@ -124,6 +154,7 @@ void rgx_destroy(rgx_context *ctx) {
   (void)hipSetDevice(ctx->device);
   for (auto &kv : ctx->tile_orders) (void)hipFree(kv.second);
   if (ctx->queue) (void)hipFree(ctx->queue);
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -216,8 +247,10 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   a.geom = (float *)b->geom.p; a.aabb = (float *)b->aabb.p; a.col = (float *)b->col.p;
   a.nodes = (float *)b->nodes.p; a.seg = (float *)b->seg.p;
   a.parent = (int32_t *)b->parent.p;
-  e = launch_build(a, stream);
-  if (e == hipSuccess) e = launch_fill(b->acc.p, n * kAccFloats, 0u, stream);
+  e = timed(ctx, RGX_KERN_BUILD, stream, [&] {
+    hipError_t r = launch_build(a, stream);
+    return r == hipSuccess ? launch_fill(b->acc.p, n * kAccFloats, 0u, stream) : r;
+  });
   if (e != hipSuccess) {
     if (fresh) rgx_bvh_destroy(b);
     return hip_fail(ctx, e, "build launch");
@@ -411,7 +444,8 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
   out.stats = stats;
   for (const ViewTable &t : tabs) {
     if (t.n_tiles == 0) continue;
-    HIP_TRY(ctx, launch_forward(sd, t, m, out, shape_for(ctx, m, t.n_tiles), stream));
+    HIP_TRY(ctx, timed(ctx, RGX_KERN_FORWARD, stream,
+                       [&] { return launch_forward(sd, t, m, out, shape_for(ctx, m, t.n_tiles), stream); }));
   }
   return RGX_OK;
 }
@@ -440,10 +474,13 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
   in.acc = (float *)bvh->acc.p;
   for (const ViewTable &t : tabs) {
     if (t.n_tiles == 0) continue;
-    HIP_TRY(ctx, launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles), stream));
+    HIP_TRY(ctx, timed(ctx, RGX_KERN_BACKWARD, stream,
+                       [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles), stream); }));
   }
-  HIP_TRY(ctx, launch_finalize_grads(sd, bvh->sh_k, (float *)bvh->acc.p, grads->means, grads->log_scales, grads->quats,
-                                     grads->density, grads->sh, grads->accumulate, stream));
+  HIP_TRY(ctx, timed(ctx, RGX_KERN_FINALIZE, stream, [&] {
+    return launch_finalize_grads(sd, bvh->sh_k, (float *)bvh->acc.p, grads->means, grads->log_scales,
+                                 grads->quats, grads->density, grads->sh, grads->accumulate, stream);
+  }));
   return RGX_OK;
 }
 
@@ -498,6 +535,29 @@ rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *b, uint64_t *keys, int
     HIP_TRY(ctx, hipMemcpy(&c, b->counters.p, 4, hipMemcpyDeviceToHost));
     *n_active = c;
   }
+  return RGX_OK;
+}
+
+rgx_status rgx_set_kernel_timing(rgx_context *ctx, int32_t enable) {
+  if (!ctx) return RGX_ERR_INVALID_ARG;
+  ctx->timing = enable != 0;
+  ctx->ev_used = 0;
+  return RGX_OK;
+}
+
+rgx_status rgx_kernel_times(rgx_context *ctx, double *ms, int64_t *launches, int32_t reset) {
+  if (!ctx || !ms || !launches) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  for (int k = 0; k < RGX_NKERN; k++) { ms[k] = 0.0; launches[k] = 0; }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  for (size_t i = 0; i < ctx->ev_used; i += 2) {
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev[i + 1]));
+    float t = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&t, ctx->ev[i], ctx->ev[i + 1]));
+    const int k = ctx->ev_kind[i / 2];
+    ms[k] += t;
+    launches[k] += 1;
+  }
+  if (reset) ctx->ev_used = 0;
   return RGX_OK;
 }
 

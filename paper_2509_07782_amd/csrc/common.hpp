@@ -19,9 +19,10 @@ constexpr int32_t kNoChild = INT32_MIN;
 enum GeomSlot { G_MU = 0, G_K2 = 3, G_M = 4, G_SIG = 13, G_L2SIG = 14 };
 
 // per-ray statistics slots (same order as the public RGX_STAT_* enum)
-enum { ST_Q = 0, ST_P, ST_SAMPLES, ST_SEGMENTS, ST_CLOSEST, ST_BOX_ONLY, ST_NODES, ST_LEAVES };
-constexpr int kNStatUsed = 8;
-constexpr int kNStat = 8;
+enum { ST_Q = 0, ST_P, ST_SAMPLES, ST_SEGMENTS, ST_CLOSEST, ST_BOX_ONLY, ST_NODES, ST_LEAVES,
+       ST_WINDOWS, ST_DFS };
+constexpr int kNStatUsed = 10;
+constexpr int kNStat = 10;
 
 struct View {
   const int32_t *tile_order;  // tile coordinates (tx | ty << 16) in launch order

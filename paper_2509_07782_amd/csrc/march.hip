@@ -722,7 +722,7 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
                                               const Ray &r, int lane, int n_active, bool alive,
                                               float a, float b, Window &w, bool stats,
                                               int32_t *err, int32_t &nodes, int32_t &leaves,
-                                              bool &fits) {
+                                              int32_t &windows, bool &fits) {
   if (op.brute_force) {
     w.kind = SRC_BRUTE;
     fits = alive;
@@ -740,6 +740,7 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
     M.rlo[lane] = lo;
     M.rhi[lane] = hi;
     __builtin_amdgcn_wave_barrier();
+    windows++;
     const int cnt = collect_window(s, M, r, lane, rays, n_active, stats, err, nodes, leaves);
     if (cnt >= 0) {
       w.count = cnt;
@@ -822,7 +823,7 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
     win.count = 0;
     win.kind = SRC_LIST;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    int32_t cnt[kNStatUsed] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t cnt[kNStatUsed] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     float prev_a = -kInf, prev_b = -kInf;
     int n_dump = 0;
 
@@ -848,7 +849,8 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
       }
       bool go;
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
-                    cnt[ST_NODES], cnt[ST_LEAVES], go);
+                    cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS], go);
+      if (stats && go && win.kind == SRC_DFS) cnt[ST_DFS]++;
       const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
       const float lo = go ? a : kInf, hi = go ? b : -kInf;
       float sg[NS], W0[NS], W1[NS], W2[NS];
@@ -863,6 +865,12 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
         const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
+        if (stats && win.kind == SRC_DFS && want && !hit) {
+          // the depth-first source visits leaves whose box met some lane's
+          // segment; count this lane's box-only leaves per segment
+          const float *bx = s.aabb + 6 * (size_t)j;
+          if (box_hit(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, lo, hi)) cnt[ST_BOX_ONLY]++;
+        }
         if (ballot(hit) == 0) return;
         if (hit) {
           nhit++;
@@ -1005,7 +1013,7 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
     win.hi = -kInf;
     win.count = 0;
     win.kind = SRC_LIST;
-    int32_t dummy_nodes = 0, dummy_leaves = 0;
+    int32_t dummy_nodes = 0, dummy_leaves = 0, dummy_windows = 0;
     float T = 1.0f;
 
     for (;;) {
@@ -1028,7 +1036,7 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
       }
       bool go;
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, false, ls.error_flag,
-                    dummy_nodes, dummy_leaves, go);
+                    dummy_nodes, dummy_leaves, dummy_windows, go);
       const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
       const float lo = go ? a : kInf, hi = go ? b : -kInf;
       float sg[NS], W0[NS], W1[NS], W2[NS];

@@ -14,8 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RGX_LIBRARY", os.path.join(HERE, "librgx.so"))
 
 RGX_OK = 0
-NSTAT = 8
-STAT_NAMES = ("Q", "P", "samples", "segments", "closest", "box_only", "nodes", "leaves")
+NSTAT = 10
+STAT_NAMES = ("Q", "P", "samples", "segments", "closest", "box_only", "nodes", "leaves",
+              "windows", "dfs_segments")
 
 
 class RgxError(RuntimeError):
@@ -54,7 +55,10 @@ class Grads(C.Structure):
 
 EXPORTS = ("rgx_create", "rgx_destroy", "rgx_build_bvh", "rgx_bvh_destroy", "rgx_bvh_size",
            "rgx_render_forward", "rgx_render_backward", "rgx_dump_hits", "rgx_bvh_debug",
-           "rgx_error_flags", "rgx_status_string", "rgx_last_error")
+           "rgx_error_flags", "rgx_set_kernel_timing", "rgx_kernel_times",
+           "rgx_status_string", "rgx_last_error")
+
+KERNEL_KINDS = ("build", "forward", "backward", "finalize")   # RGX_KERN_* order
 
 _LIB = None
 
@@ -91,6 +95,10 @@ def load():
     L.rgx_bvh_debug.restype = st
     L.rgx_error_flags.argtypes = [vp, C.POINTER(C.c_int32), vp]
     L.rgx_error_flags.restype = st
+    L.rgx_set_kernel_timing.argtypes = [vp, C.c_int32]
+    L.rgx_set_kernel_timing.restype = st
+    L.rgx_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+    L.rgx_kernel_times.restype = st
     L.rgx_status_string.argtypes = [st]
     L.rgx_status_string.restype = C.c_char_p
     L.rgx_last_error.argtypes = [vp]
@@ -160,6 +168,17 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_kernel_timing(self, enable: bool):
+        check(load().rgx_set_kernel_timing(self.h, int(bool(enable))), self.h, "set_kernel_timing")
+
+    def kernel_times(self, reset: bool = True) -> dict:
+        """{kind: (total ms, launches)} of the launches recorded since timing
+        was enabled (or the last reset); waits for the recorded events."""
+        n = len(KERNEL_KINDS)
+        ms, cnt = (C.c_double * n)(), (C.c_int64 * n)()
+        check(load().rgx_kernel_times(self.h, ms, cnt, int(bool(reset))), self.h, "kernel_times")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     def error_flags(self, stream=0) -> int:
         f = C.c_int32(0)
