@@ -120,7 +120,7 @@ enum {
   RGX_STAT_NODES,        /* BVH nodes loaded by the wave for the segment collections */
   RGX_STAT_LEAVES,       /* leaves the wave visited for the segment collections */
   RGX_STAT_WINDOWS,      /* window collections the wave made (attempts included) */
-  RGX_STAT_DFS,          /* segments whose candidates came from a depth-first traversal */
+  RGX_STAT_CHUNKED,      /* segments whose candidates were collected in several Z chunks */
   RGX_NSTAT = 10
 };
 
@@ -177,7 +177,8 @@ rgx_status rgx_dump_hits(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera 
      perm  [n] int32  user index of the i-th Z-ordered Gaussian
      aabb  [n,6] float leaf boxes (lo xyz, hi xyz) in Z order
      nodes [max(n-1,1), 16] float internal nodes: left box lo/hi, right box lo/hi,
-           children as int bits (>= 0 internal, < 0 leaf ~i, INT32_MIN none)
+           children as int bits (>= 0 internal, < 0 leaf ~i, INT32_MIN none) in
+           words 3 and 7, the node's first and last leaf index in words 11 and 15
      n_active (host) number of active Gaussians. */
 rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *bvh, uint64_t *keys, int32_t *perm,
                          float *aabb, float *nodes, int64_t *n_active, hipStream_t stream);

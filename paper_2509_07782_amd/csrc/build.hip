@@ -342,8 +342,8 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
   if (n == 1 && i == 0) {
     nodes[0] = make_float4(aabb[0], aabb[1], aabb[2], __int_as_float(~0));
     nodes[1] = make_float4(aabb[3], aabb[4], aabb[5], __int_as_float(kNoChild));
-    nodes[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    nodes[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+    nodes[2] = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
+    nodes[3] = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
     return;
   }
   if (i >= n - 1) return;
@@ -377,8 +377,10 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
   float4 *nd = nodes + 4 * (size_t)i;
   nd[0] = make_float4(bl[0], bl[1], bl[2], __int_as_float(left));
   nd[1] = make_float4(bl[3], bl[4], bl[5], __int_as_float(right));
-  nd[2] = make_float4(br[0], br[1], br[2], 0.0f);
-  nd[3] = make_float4(br[3], br[4], br[5], 0.0f);
+  // the node's leaf (Z index) range [lo, hi]; the split is implied by the
+  // left link (gamma), so range-restricted traversals can prune children
+  nd[2] = make_float4(br[0], br[1], br[2], __int_as_float(lo));
+  nd[3] = make_float4(br[3], br[4], br[5], __int_as_float(hi));
 }
 
 // ---------------------------------------------------------------------------

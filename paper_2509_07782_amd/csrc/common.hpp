@@ -20,7 +20,7 @@ enum GeomSlot { G_MU = 0, G_K2 = 3, G_M = 4, G_SIG = 13, G_L2SIG = 14 };
 
 // per-ray statistics slots (same order as the public RGX_STAT_* enum)
 enum { ST_Q = 0, ST_P, ST_SAMPLES, ST_SEGMENTS, ST_CLOSEST, ST_BOX_ONLY, ST_NODES, ST_LEAVES,
-       ST_WINDOWS, ST_DFS };
+       ST_WINDOWS, ST_CHUNKED };
 constexpr int kNStatUsed = 10;
 constexpr int kNStat = 10;
 

@@ -285,13 +285,14 @@ __device__ __forceinline__ int pop_tile(int32_t *queue, int n_tiles, int home, i
   return -1;
 }
 
-template <int NS>
-__device__ __forceinline__ void sample_positions(bool grid, int seg_i, float a, float dt, float tn,
-                                                 float *t) {
-#pragma unroll
-  for (int k = 0; k < NS; k++)
-    t[k] = grid ? fmaf((float)(seg_i * NS + k) + 0.5f, dt, tn) : fmaf((float)k + 0.5f, dt, a);
-}
+// Midpoint sample positions of a segment, t_k = o + (i0 + k + 1/2) dt: on the
+// fixed grid o = t_n and i0 = N_s * segment index, otherwise o = a, i0 = 0.
+// Evaluated on use (three registers instead of N_s).
+struct Samples {
+  float o, dt;
+  int i0;
+  __device__ __forceinline__ float t(int k) const { return fmaf((float)(i0 + k) + 0.5f, dt, o); }
+};
 
 // Eq. 5 with d_i = a (unit direction from the camera centre).
 __device__ __forceinline__ float adaptive_dt(const MarchOpts &op, float a, float T) {
@@ -311,11 +312,11 @@ struct SegState {
 // The N_S sample weights of one Gaussian for one lane:
 // w_k = sigma~ exp(-q(t_k)/2) if q(t_k) <= k^2 else 0.
 template <int NS>
-__device__ __forceinline__ void sample_weights(const Gauss &g, const Chord &c, const float *ts,
+__device__ __forceinline__ void sample_weights(const Gauss &g, const Chord &c, const Samples &sp,
                                                float *w) {
 #pragma unroll
   for (int k = 0; k < NS; k++) {
-    const float u = ts[k] - c.ts;
+    const float u = sp.t(k) - c.ts;
     const float q = fmaf(c.A * u, u, c.h2);
     const float e = __builtin_amdgcn_exp2f(fmaf(-q, kHalfLog2e, g.l2sig));
     w[k] = q <= g.k2 ? e : 0.0f;
@@ -326,11 +327,13 @@ __device__ __forceinline__ void sample_weights(const Gauss &g, const Chord &c, c
 template <int NS>
 __device__ __forceinline__ bool segment(const MarchOpts &op, bool grid, const SegState &ss,
                                         float tn, float T, float &a, float &b, float &dt,
-                                        float *ts) {
+                                        Samples &sp) {
   a = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
   dt = op.adaptive ? adaptive_dt(op, a, T) : op.dt;
   b = grid ? fmaf((float)((ss.seg_i + 1) * NS), op.dt, tn) : fmaf((float)NS, dt, a);
-  sample_positions<NS>(grid, ss.seg_i, a, dt, tn, ts);
+  sp.o = grid ? tn : a;
+  sp.dt = dt;
+  sp.i0 = grid ? ss.seg_i * NS : 0;
   return b > a;
 }
 
@@ -428,26 +431,29 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
 }
 
 // ---------------------------------------------------------------------------
-// Window collection.  For a per-lane depth window [lo, hi] (several segments
-// long) the wave gathers every Gaussian whose chord meets some lane's window,
-// with the 64-bit mask of those lanes and the extreme chord ends over them.
-// The traversal is node-parallel: a FIFO frontier of (node, ray mask) lives
-// in LDS and each round hands up to 64 frontier nodes to the 64 lanes, which
-// load them independently and test both child boxes against the rays of the
-// node's mask.  Leaves are staged and chord-tested 64 at a time.  The list is
-// then sorted by Gaussian (Z) index, so every ray meets its Gaussians in Z
-// order whatever window, packet or traversal produced the list -- the same
-// order as the depth-first fallback and the brute-force enumeration.
+// Window collection.  For a per-lane depth window [lo, hi] the wave gathers
+// every Gaussian whose chord meets some lane's window, with the 64-bit mask of
+// those lanes and the extreme chord ends over them, restricted to the Z-index
+// range [z0, z1).  The traversal is node-parallel: a FIFO frontier of
+// (node, ray mask, first leaf) lives in LDS and each round hands up to 64
+// frontier nodes to the 64 lanes, which load them independently and test both
+// child boxes against the rays of the node's mask.  Leaves are staged and
+// chord-tested 64 at a time.  When the frontier or the list would overflow,
+// z1 is lowered (a radix select over the pending Z indices) and everything at
+// or beyond it is dropped, so the result is always complete for [z0, z1);
+// the caller continues from z1 with another chunk.  The list is finally
+// sorted by Z index, so every ray meets its Gaussians in Z order whatever
+// window, chunking or packet produced the list -- the order of brute force.
 
 constexpr int kRingCap = 256;    // frontier entries (power of two)
-constexpr int kStageCap = 192;   // staged leaves: < 64 left over + 128 per round
+constexpr int kStageCap = 160;   // staged leaves; a round adds at most 2 per node
 constexpr int kListCap = 256;    // window list entries (LDS budget: 3 waves per SIMD)
 
 struct WaveMem {
   float rdx[64], rdy[64], rdz[64], rix[64], riy[64], riz[64], rlo[64], rhi[64];
   union {
     struct {                       // during collection
-      int32_t ring_id[kRingCap];
+      int32_t ring_id[kRingCap], ring_first[kRingCap];
       uint32_t ring_mlo[kRingCap], ring_mhi[kRingCap];
       int32_t st_id[kStageCap];
       uint32_t st_mlo[kStageCap], st_mhi[kStageCap];
@@ -489,12 +495,93 @@ __device__ __forceinline__ Gauss load_gauss_lane(const float *geom, int j) {
   return g;
 }
 
-// Bitonic sort (by Gaussian index) of the window list's order keys in LDS.
-__device__ __forceinline__ void sort_list(WaveMem &M, int lane, int count) {
+// Largest z in [zlo, zhi] such that at most `target` of the wave's values
+// (V per lane, where ok) are below z.  zlo, zhi and the result are uniform.
+template <int V>
+__device__ __forceinline__ int select_cut(const int (&v)[V], const bool (&ok)[V], int zlo, int zhi,
+                                          int target) {
+  while (zlo < zhi) {
+    const int mid = zlo + ((zhi - zlo + 1) >> 1);
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < V; k++) c += __popcll(ballot(ok[k] && v[k] < mid));
+    if (c <= target) zlo = mid;
+    else zhi = mid - 1;
+  }
+  return zlo;
+}
+
+// Keeps the list entries with index < z1 (order preserved); returns the
+// count.  64 entries at a time: a write never passes an unread entry.
+__device__ __forceinline__ int compact_list(WaveMem &M, int lane, int count, int z1) {
+  const uint64_t below = lanes_below(lane);
+  int base = 0;
+  for (int e0 = 0; e0 < count; e0 += 64) {
+    const int e = e0 + lane;
+    int id = 0;
+    uint32_t mlo = 0, mhi = 0;
+    float tin = 0.0f, tout = 0.0f;
+    bool keep = false;
+    if (e < count) {
+      id = M.l_id[e]; mlo = M.l_mlo[e]; mhi = M.l_mhi[e]; tin = M.l_tin[e]; tout = M.l_tout[e];
+      keep = id < z1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t b = ballot(keep);
+    if (keep) {
+      const int pos = base + __popcll(b & below);
+      M.l_id[pos] = id; M.l_mlo[pos] = mlo; M.l_mhi[pos] = mhi; M.l_tin[pos] = tin; M.l_tout[pos] = tout;
+    }
+    base += __popcll(b);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return base;
+}
+
+// Keeps the pending frontier entries whose first leaf is below z1 (order
+// preserved, same scheme); returns the new tail.
+__device__ __forceinline__ int compact_ring(WaveMem &M, int lane, int head, int tail, int z1) {
+  const uint64_t below = lanes_below(lane);
+  int base = head;
+  for (int e0 = head; e0 < tail; e0 += 64) {
+    const int e = e0 + lane;
+    const int slot = e & (kRingCap - 1);
+    int id = 0, first = 0;
+    uint32_t mlo = 0, mhi = 0;
+    bool keep = false;
+    if (e < tail) {
+      id = M.u.c.ring_id[slot]; first = M.u.c.ring_first[slot];
+      mlo = M.u.c.ring_mlo[slot]; mhi = M.u.c.ring_mhi[slot];
+      keep = first < z1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t b = ballot(keep);
+    if (keep) {
+      const int d = (base + __popcll(b & below)) & (kRingCap - 1);
+      M.u.c.ring_id[d] = id; M.u.c.ring_first[d] = first; M.u.c.ring_mlo[d] = mlo; M.u.c.ring_mhi[d] = mhi;
+    }
+    base += __popcll(b);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return base;
+}
+
+// Bitonic sort (by Gaussian index) of the window list's order keys in LDS;
+// entries with index >= z1 sort last and are dropped.  Returns the count.
+__device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int z1) {
   int p2 = 1;
   while (p2 < count) p2 <<= 1;
-  for (int e = lane; e < p2; e += 64)
-    M.u.order[e] = e < count ? ((uint64_t)(uint32_t)M.l_id[e] << 32) | (uint32_t)e : ~0ull;
+  int valid = 0;
+  for (int e0 = 0; e0 < p2; e0 += 64) {
+    const int e = e0 + lane;
+    bool ok = false;
+    if (e < p2) {
+      const int id = e < count ? M.l_id[e] : 0;
+      ok = e < count && id < z1;
+      M.u.order[e] = ok ? ((uint64_t)(uint32_t)id << 32) | (uint32_t)e : ~0ull;
+    }
+    valid += __popcll(ballot(ok));
+  }
   for (int k = 2; k <= p2; k <<= 1) {
     for (int j = k >> 1; j >= 1; j >>= 1) {
       __builtin_amdgcn_wave_barrier();
@@ -509,79 +596,111 @@ __device__ __forceinline__ void sort_list(WaveMem &M, int lane, int count) {
     }
   }
   __builtin_amdgcn_wave_barrier();
+  return valid;
 }
 
-// Returns the number of list entries, -1 when a capacity was exceeded (the
-// caller retries with a shorter window) or -2 on a malformed tree.
+// Collects the list for the rays in `rays` (windows in M.rlo / M.rhi) and
+// the Z range [z0, z1); z1 may be lowered.  Returns the number of list
+// entries, or -1 on a malformed tree (error flag set).
 __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, int lane,
-                              uint64_t rays, int n_active, bool stats, int32_t *err,
-                              int32_t &nodes_out, int32_t &leaves_out) {
-  if (n_active <= 0 || rays == 0) return 0;
+                              uint64_t rays, int n_active, int z0, int &z1, bool stats,
+                              int32_t *err, int32_t &nodes_out, int32_t &leaves_out) {
+  if (n_active <= 0 || rays == 0 || z0 >= z1) return 0;
   const int n_inner = n_active > 1 ? n_active - 1 : 1;
   int head = 0, tail = 1, staged = 0, count = 0, visits = 0;
   if (lane == 0) {
     M.u.c.ring_id[0] = 0;
+    M.u.c.ring_first[0] = 0;
     M.u.c.ring_mlo[0] = (uint32_t)rays;
     M.u.c.ring_mhi[0] = (uint32_t)(rays >> 32);
   }
   const uint64_t below = lanes_below(lane);
   for (;;) {
     __builtin_amdgcn_wave_barrier();
-    const int n = min(64, tail - head);
+    const int n = min(min(64, tail - head), (kStageCap - staged) >> 1);
     if (n > 0) {
       int id = 0;
       uint64_t mk = 0;
+      bool live = false;
       if (lane < n) {
         const int slot = (head + lane) & (kRingCap - 1);
         id = M.u.c.ring_id[slot];
         mk = join64(M.u.c.ring_mlo[slot], M.u.c.ring_mhi[slot]);
+        live = M.u.c.ring_first[slot] < z1;      // else cut off by a later z1
       }
       head += n;
-      visits += n;
-      if (visits > n_inner) { if (err) *err = 2; return -2; }
+      visits += __popcll(ballot(live));
+      if (visits > n_inner) { if (err) *err = 2; return -1; }
       vf4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0}, c = {0, 0, 0, 0}, d = {0, 0, 0, 0};
-      if (lane < n) {
+      if (live) {
         const vf4 *np = reinterpret_cast<const vf4 *>(s.nodes) + 4 * id;
         a = np[0]; b = np[1]; c = np[2]; d = np[3];
       }
-      const int cl = lane < n ? __float_as_int(a.w) : kNoChild;
-      const int cr = lane < n ? __float_as_int(b.w) : kNoChild;
-      const bool bad = lane < n && ((cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
-                                    (cr != kNoChild && (cr >= 0 ? cr >= n_inner : ~cr >= n_active)));
-      if (ballot(bad)) { if (err) *err = 3; return -2; }
+      const int cl = live ? __float_as_int(a.w) : kNoChild;
+      const int cr = live ? __float_as_int(b.w) : kNoChild;
+      const int nlo = __float_as_int(c.w), nhi = __float_as_int(d.w);
+      const int gamma = cl < 0 ? ~cl : cl;       // left range [nlo, gamma], right [gamma+1, nhi]
+      const bool bad = live && ((cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
+                                (cr != kNoChild && ((cr >= 0 ? cr >= n_inner : ~cr >= n_active) ||
+                                                    !(0 <= nlo && nlo <= gamma && gamma < nhi &&
+                                                      nhi < n_active))));
+      if (ballot(bad)) { if (err) *err = 3; return -1; }
+      const bool inL = live && nlo < z1 && gamma >= z0;
+      const bool inR = live && cr != kNoChild && gamma + 1 < z1 && nhi >= z0;
       uint64_t mL = 0, mR = 0;
       for (uint64_t rem = rays; rem; rem &= rem - 1) {
         const int r = __builtin_ctzll(rem);
         const Ray q = lds_ray(M, self, r);
         const float lo = M.rlo[r], hi = M.rhi[r];
         if ((mk >> r) & 1) {
-          if (box_hit(a.x, a.y, a.z, b.x, b.y, b.z, q, lo, hi)) mL |= 1ull << r;
-          if (cr != kNoChild && box_hit(c.x, c.y, c.z, d.x, d.y, d.z, q, lo, hi)) mR |= 1ull << r;
+          if (inL && box_hit(a.x, a.y, a.z, b.x, b.y, b.z, q, lo, hi)) mL |= 1ull << r;
+          if (inR && box_hit(c.x, c.y, c.z, d.x, d.y, d.z, q, lo, hi)) mR |= 1ull << r;
         }
       }
       // children, in lane order, left before right
-      const bool lI = mL != 0 && cl >= 0, rI = mR != 0 && cr >= 0 && cr != kNoChild;
-      const bool lL = mL != 0 && cl < 0 && cl != kNoChild, rL = mR != 0 && cr < 0 && cr != kNoChild;
+      bool lI = mL != 0 && cl >= 0, rI = mR != 0 && cr >= 0;
+      bool lL = mL != 0 && cl < 0, rL = mR != 0 && cr < 0;
       {
+        int tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
+        if (tail + tot - head > kRingCap) {
+          // frontier overflow: lower z1 to half the pending subtrees
+          int v[6];
+          bool ok[6];
+          const int pend = tail - head;
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int e = lane + 64 * k;
+            ok[k] = e < pend;
+            v[k] = ok[k] ? M.u.c.ring_first[(head + e) & (kRingCap - 1)] : 0;
+          }
+          v[4] = nlo; ok[4] = lI;
+          v[5] = gamma + 1; ok[5] = rI;
+          z1 = select_cut(v, ok, z0 + 1, z1, kRingCap / 2);
+          tail = compact_ring(M, lane, head, tail, z1);
+          lI = lI && nlo < z1;
+          rI = rI && gamma + 1 < z1;
+          lL = lL && gamma < z1;
+          rL = rL && gamma + 1 < z1;
+          tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
+        }
         const uint64_t b1 = ballot(lI || rI), b2 = ballot(lI && rI);
-        const int tot = __popcll(b1) + __popcll(b2);
-        if (tail + tot - head > kRingCap) return -1;
         int pos = tail + __popcll(b1 & below) + __popcll(b2 & below);
         if (lI) {
           const int slot = pos & (kRingCap - 1);
-          M.u.c.ring_id[slot] = cl; M.u.c.ring_mlo[slot] = (uint32_t)mL; M.u.c.ring_mhi[slot] = (uint32_t)(mL >> 32);
+          M.u.c.ring_id[slot] = cl; M.u.c.ring_first[slot] = nlo;
+          M.u.c.ring_mlo[slot] = (uint32_t)mL; M.u.c.ring_mhi[slot] = (uint32_t)(mL >> 32);
           pos++;
         }
         if (rI) {
           const int slot = pos & (kRingCap - 1);
-          M.u.c.ring_id[slot] = cr; M.u.c.ring_mlo[slot] = (uint32_t)mR; M.u.c.ring_mhi[slot] = (uint32_t)(mR >> 32);
+          M.u.c.ring_id[slot] = cr; M.u.c.ring_first[slot] = gamma + 1;
+          M.u.c.ring_mlo[slot] = (uint32_t)mR; M.u.c.ring_mhi[slot] = (uint32_t)(mR >> 32);
         }
         tail += tot;
       }
       {
         const uint64_t b1 = ballot(lL || rL), b2 = ballot(lL && rL);
         const int tot = __popcll(b1) + __popcll(b2);
-        if (staged + tot > kStageCap) return -1;
         int pos = staged + __popcll(b1 & below) + __popcll(b2 & below);
         if (lL) { M.u.c.st_id[pos] = ~cl; M.u.c.st_mlo[pos] = (uint32_t)mL; M.u.c.st_mhi[pos] = (uint32_t)(mL >> 32); pos++; }
         if (rL) { M.u.c.st_id[pos] = ~cr; M.u.c.st_mlo[pos] = (uint32_t)mR; M.u.c.st_mhi[pos] = (uint32_t)(mR >> 32); }
@@ -595,10 +714,13 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       const int k = min(64, staged);
       int j = 0;
       uint64_t mk = 0;
-      if (lane < k) { j = M.u.c.st_id[lane]; mk = join64(M.u.c.st_mlo[lane], M.u.c.st_mhi[lane]); }
+      if (lane < k) {
+        j = M.u.c.st_id[lane];
+        mk = j < z1 ? join64(M.u.c.st_mlo[lane], M.u.c.st_mhi[lane]) : 0ull;
+      }
       uint64_t hitm = 0;
       float tmin = kInf, tmax = -kInf;
-      if (lane < k) {
+      if (mk != 0) {
         const Gauss g = load_gauss_lane(s.geom, j);
         for (uint64_t rem = mk; rem; rem &= rem - 1) {
           const int r = __builtin_ctzll(rem);
@@ -615,10 +737,26 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         }
       }
       leaves_out += k;
-      const bool keep = hitm != 0;
+      bool keep = hitm != 0;
+      int tot = __popcll(ballot(keep));
+      if (count + tot > kListCap) {
+        // list overflow: lower z1 so that half the list remains
+        int v[kListCap / 64 + 1];
+        bool ok[kListCap / 64 + 1];
+#pragma unroll
+        for (int q = 0; q < kListCap / 64; q++) {
+          const int e = lane + 64 * q;
+          ok[q] = e < count;
+          v[q] = ok[q] ? M.l_id[e] : 0;
+        }
+        v[kListCap / 64] = j;
+        ok[kListCap / 64] = keep;
+        z1 = select_cut(v, ok, z0 + 1, z1, kListCap / 2);
+        count = compact_list(M, lane, count, z1);
+        keep = keep && j < z1;
+        tot = __popcll(ballot(keep));
+      }
       const uint64_t bk = ballot(keep);
-      const int tot = __popcll(bk);
-      if (count + tot > kListCap) return -1;
       if (keep) {
         const int pos = count + __popcll(bk & below);
         M.l_id[pos] = j;
@@ -646,25 +784,22 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
     if (done && staged == 0) break;
   }
   nodes_out += visits;
-  sort_list(M, lane, count);
-  return count;
+  return sort_list(M, lane, count, z1);
 }
 
 // ---------------------------------------------------------------------------
-// Sources of a segment's candidate Gaussians, all in Z-index order:
-// the window list (LDS), every active Gaussian (brute force) or, when a
-// window cannot fit even one segment, a depth-first traversal.
+// Sources of a segment's candidate Gaussians, both in Z-index order: the
+// window list (LDS) or every active Gaussian (brute force).
 
-enum SourceKind { SRC_LIST = 0, SRC_BRUTE = 1, SRC_DFS = 2 };
+enum SourceKind { SRC_LIST = 0, SRC_BRUTE = 1 };
 
 // Calls fn(j, lane_may_hit) for every candidate; lane_may_hit is false for
 // lanes the candidate cannot touch (list mask).  `a_min`/`b_max` bound the
 // live lanes' segments for the list's uniform pre-check.
 template <class Fn>
-__device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, const WaveMem &M,
-                                                   int count, int lane, float a_min, float b_max,
-                                                   int n_active, const Ray &r, float lo, float hi,
-                                                   int32_t *err, Fn &&fn) {
+__device__ __forceinline__ void for_each_candidate(int kind, const WaveMem &M, int count,
+                                                   int lane, float a_min, float b_max,
+                                                   int n_active, Fn &&fn) {
   if (kind == SRC_LIST) {
     // 64 entries at a time: lane i holds entry base + i; the depth pre-check
     // is one ballot, and the surviving entries are read back with readlane
@@ -687,12 +822,8 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
         fn(__builtin_amdgcn_readlane(id, src), ((mk >> lane) & 1) != 0);
       }
     }
-  } else if (kind == SRC_BRUTE) {
-    for (int e = 0; e < n_active; e++) fn(e, true);
   } else {
-    LeafIter it;
-    it.init(n_active, false);
-    for (int j; (j = it.next(s, r, lo, hi, err)) >= 0;) fn(j, true);
+    for (int e = 0; e < n_active; e++) fn(e, true);
   }
 }
 
@@ -709,15 +840,18 @@ __device__ __forceinline__ float wave_max(float v) {
 
 // Per-wave window bookkeeping shared by forward and backward.
 struct Window {
-  float len, len_min, len_max;   // uniform window length and its bounds
-  bool valid;                    // per lane: the current list covers this lane
+  float len, len_min, len_max;   // uniform window length beyond the segment, and its bounds
+  bool valid;                    // per lane: the current list covers this lane's later segments
   float hi;                      // per lane window end
   int count;                     // uniform list size
   int kind;                      // SourceKind of the current candidates
+  int z1;                        // uniform end of the list's Z range (n_active: complete)
+  bool chunked;                  // uniform: this segment's candidates come in Z chunks
 };
 
 // Makes sure every live lane whose segment fits its window can march; when
-// no live lane can, collects a new window for all live lanes.
+// no live lane can, collects a new window for all live lanes.  A window that
+// had to be cut in Z serves the current segment only, chunk by chunk.
 __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts &op, WaveMem &M,
                                               const Ray &r, int lane, int n_active, bool alive,
                                               float a, float b, Window &w, bool stats,
@@ -725,47 +859,69 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
                                               int32_t &windows, bool &fits) {
   if (op.brute_force) {
     w.kind = SRC_BRUTE;
+    w.chunked = false;
     fits = alive;
     return;
   }
   fits = alive && w.valid && b <= w.hi;
-  if (ballot(fits) != 0 || ballot(alive) == 0) return;
+  if (ballot(fits) != 0 || ballot(alive) == 0) {
+    w.chunked = false;
+    return;
+  }
   const uint64_t rays = ballot(alive);
-  for (;;) {
-    float lo = kInf, hi = -kInf;
-    if (alive) {
-      lo = a;
-      hi = fmaxf(a + w.len, b);
-    }
-    M.rlo[lane] = lo;
-    M.rhi[lane] = hi;
-    __builtin_amdgcn_wave_barrier();
-    windows++;
-    const int cnt = collect_window(s, M, r, lane, rays, n_active, stats, err, nodes, leaves);
-    if (cnt >= 0) {
-      w.count = cnt;
-      w.kind = SRC_LIST;
-      w.valid = alive;
-      w.hi = hi;
-      if (cnt < kListCap / 4) w.len = fminf(w.len * 1.5f, w.len_max);
-      break;
-    }
-    if (cnt == -2 || w.len <= w.len_min) {
-      // no window fits: this segment takes the depth-first path
-      w.kind = SRC_DFS;
-      w.valid = false;
-      break;
-    }
-    w.len = fmaxf(w.len * 0.5f, w.len_min);
+  const float hi = alive ? fmaxf(a + w.len, b) : -kInf;
+  M.rlo[lane] = alive ? a : kInf;
+  M.rhi[lane] = hi;
+  __builtin_amdgcn_wave_barrier();
+  windows++;
+  int z1 = n_active;
+  const int cnt = collect_window(s, M, r, lane, rays, n_active, 0, z1, stats, err, nodes, leaves);
+  w.kind = SRC_LIST;
+  w.count = cnt > 0 ? cnt : 0;
+  w.z1 = cnt >= 0 ? z1 : n_active;     // a malformed tree ends the rays (error flag set)
+  w.chunked = w.z1 < n_active;
+  if (!w.chunked) {
+    w.valid = alive;
+    w.hi = hi;
+    if (cnt < kListCap / 4) w.len = fminf(fmaxf(w.len * 1.5f, w.len_min), w.len_max);
+  } else {
+    w.valid = false;
+    w.len = w.len * 0.5f < w.len_min ? 0.0f : w.len * 0.5f;
   }
   fits = alive;
+}
+
+// In chunked mode, collects the candidates of the next Z chunk for the lanes
+// in `lanes` over their segments [a, b] (from Z index `z0`); false when the
+// segment's candidates are exhausted.
+__device__ __forceinline__ bool next_chunk(const SceneDev &s, WaveMem &M, const Ray &r, int lane,
+                                           int n_active, bool lanes, float a, float b, int z0,
+                                           Window &w, bool stats, int32_t *err, int32_t &nodes,
+                                           int32_t &leaves, int32_t &windows) {
+  if (!w.chunked || z0 >= n_active) return false;
+  const uint64_t rays = ballot(lanes);
+  if (rays == 0) return false;
+  M.rlo[lane] = lanes ? a : kInf;
+  M.rhi[lane] = lanes ? b : -kInf;
+  __builtin_amdgcn_wave_barrier();
+  windows++;
+  int z1 = n_active;
+  const int cnt = collect_window(s, M, r, lane, rays, n_active, z0, z1, stats, err, nodes, leaves);
+  if (cnt < 0) {
+    w.count = 0;
+    w.z1 = n_active;
+    return false;
+  }
+  w.count = cnt;
+  w.z1 = z1;
+  return true;
 }
 
 // ---------------------------------------------------------------------------
 // Forward kernel (and the hit-dump variant).
 
 template <int NS, bool DUMP, bool STATS>
-__global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, MarchOpts op,
+__global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, ViewTable vt, MarchOpts op,
                                                    FwdOut out, LaunchShape ls) {
   __shared__ WaveMem M;
   const int lane = threadIdx.x;
@@ -815,13 +971,16 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
     ss.cl_lo = tn;
     const float dS = op.dt * (float)NS;
     Window win;
-    win.len_min = (float)NS * (op.adaptive ? op.dt_max : op.dt) * 1.0001f + 1e-6f;
-    win.len = (float)op.window_segments * win.len_min;
-    win.len_max = fmaxf(8.0f * win.len_min, 2.0f * win.len);
+    const float seg_max = (float)NS * (op.adaptive ? op.dt_max : op.dt);
+    win.len_min = (float)NS * (op.adaptive ? op.dt_min : op.dt);
+    win.len = (float)op.window_segments * seg_max;
+    win.len_max = fmaxf(8.0f * seg_max, 2.0f * win.len);
     win.valid = false;
     win.hi = -kInf;
     win.count = 0;
     win.kind = SRC_LIST;
+    win.z1 = n_active;
+    win.chunked = false;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     int32_t cnt[kNStatUsed] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     float prev_a = -kInf, prev_b = -kInf;
@@ -836,21 +995,19 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
         if (!(a0 < tf) || !(T > op.t_eps)) ss.alive = false;
       }
       if (ballot(ss.alive) == 0) break;
-      float a = 0.0f, b = 0.0f, dt = op.dt, ts[NS];
+      float a = 0.0f, b = 0.0f, dt = op.dt;
+      Samples sp;
       if (ss.alive) {
-        if (!segment<NS>(op, grid, ss, tn, T, a, b, dt, ts)) {   // no progress in FP32
+        if (!segment<NS>(op, grid, ss, tn, T, a, b, dt, sp)) {   // no progress in FP32
           ss.alive = false;
           if (ls.error_flag) *ls.error_flag = 4;
         }
       }
-      if (!ss.alive) {
-#pragma unroll
-        for (int k = 0; k < NS; k++) ts[k] = 0.0f;
-      }
+      if (!ss.alive) { sp.o = 0.0f; sp.dt = 0.0f; sp.i0 = 0; }
       bool go;
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
                     cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS], go);
-      if (stats && go && win.kind == SRC_DFS) cnt[ST_DFS]++;
+      if (stats && go && win.chunked) cnt[ST_CHUNKED]++;
       const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
       const float lo = go ? a : kInf, hi = go ? b : -kInf;
       float sg[NS], W0[NS], W1[NS], W2[NS];
@@ -858,19 +1015,12 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
       int nhit = 0;
 
-      for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, lo, hi,
-                         ls.error_flag, [&](int j, bool may) {
+      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j, bool may) {
         const bool want = go && may;
         if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
-        if (stats && win.kind == SRC_DFS && want && !hit) {
-          // the depth-first source visits leaves whose box met some lane's
-          // segment; count this lane's box-only leaves per segment
-          const float *bx = s.aabb + 6 * (size_t)j;
-          if (box_hit(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, lo, hi)) cnt[ST_BOX_ONLY]++;
-        }
         if (ballot(hit) == 0) return;
         if (hit) {
           nhit++;
@@ -885,7 +1035,7 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
           float cr, cg, cb;
           colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
           float wk[NS];
-          sample_weights<NS>(g, c, ts, wk);
+          sample_weights<NS>(g, c, sp, wk);
 #pragma unroll
           for (int k = 0; k < NS; k++) {
             sg[k] += wk[k];
@@ -894,16 +1044,16 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
             W2[k] = fmaf(wk[k], cb, W2[k]);
           }
         }
-      });
+      }); while (next_chunk(s, M, r, lane, n_active, go, a, b, win.z1, win, stats, ls.error_flag,
+                            cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS]));
 
       // an empty segment restarts at the next closest hit: inside the window
       // from the list, otherwise through a closest-hit traversal
       const bool empty = go && nhit == 0;
       float best = kInf;
-      if (op.ess && win.kind == SRC_LIST && ballot(empty)) {
+      if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r, lo, hi,
-                           ls.error_flag, [&](int j, bool may) {
+        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, [&](int j, bool may) {
           const bool want = empty && may;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
@@ -916,7 +1066,7 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
           if (stats) { cnt[ST_SEGMENTS]++; cnt[ST_P] += nhit; }
 #pragma unroll
           for (int k = 0; k < NS; k++) {
-            if (ts[k] < tf) {
+            if (sp.t(k) < tf) {
               if (stats) cnt[ST_SAMPLES]++;
               if (sg[k] > 0.0f) {
                 const float x = sg[k] * dt;
@@ -933,7 +1083,6 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
         }
         step_after(op, grid, nhit > 0, best, tn, dS, b, ss);
       }
-      if (win.kind == SRC_DFS) win.kind = SRC_LIST;
     }
 
     if (stats) cnt[ST_BOX_ONLY] += M.cnt_box[lane];
@@ -959,7 +1108,7 @@ __global__ __launch_bounds__(kWave) void k_forward(SceneDev s, ViewTable vt, Mar
 // the wave before one atomic per accumulator slot.
 
 template <int NS>
-__global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, MarchOpts op,
+__global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s, ViewTable vt, MarchOpts op,
                                                     BwdIn in, LaunchShape ls) {
   __shared__ WaveMem M;
   const int lane = threadIdx.x;
@@ -1006,13 +1155,16 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
     ss.cl_lo = tn;
     const float dS = op.dt * (float)NS;
     Window win;
-    win.len_min = (float)NS * (op.adaptive ? op.dt_max : op.dt) * 1.0001f + 1e-6f;
-    win.len = (float)op.window_segments * win.len_min;
-    win.len_max = fmaxf(8.0f * win.len_min, 2.0f * win.len);
+    const float seg_max = (float)NS * (op.adaptive ? op.dt_max : op.dt);
+    win.len_min = (float)NS * (op.adaptive ? op.dt_min : op.dt);
+    win.len = (float)op.window_segments * seg_max;
+    win.len_max = fmaxf(8.0f * seg_max, 2.0f * win.len);
     win.valid = false;
     win.hi = -kInf;
     win.count = 0;
     win.kind = SRC_LIST;
+    win.z1 = n_active;
+    win.chunked = false;
     int32_t dummy_nodes = 0, dummy_leaves = 0, dummy_windows = 0;
     float T = 1.0f;
 
@@ -1023,17 +1175,15 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
         if (!(a0 < tf) || !(T > op.t_eps)) ss.alive = false;
       }
       if (ballot(ss.alive) == 0) break;
-      float a = 0.0f, b = 0.0f, dt = op.dt, ts[NS];
+      float a = 0.0f, b = 0.0f, dt = op.dt;
+      Samples sp;
       if (ss.alive) {
-        if (!segment<NS>(op, grid, ss, tn, T, a, b, dt, ts)) {
+        if (!segment<NS>(op, grid, ss, tn, T, a, b, dt, sp)) {
           ss.alive = false;
           if (ls.error_flag) *ls.error_flag = 4;
         }
       }
-      if (!ss.alive) {
-#pragma unroll
-        for (int k = 0; k < NS; k++) ts[k] = 0.0f;
-      }
+      if (!ss.alive) { sp.o = 0.0f; sp.dt = 0.0f; sp.i0 = 0; }
       bool go;
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, false, ls.error_flag,
                     dummy_nodes, dummy_leaves, dummy_windows, go);
@@ -1045,8 +1195,7 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
       int nhit = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
-      for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, lo, hi,
-                         ls.error_flag, [&](int j, bool may) {
+      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j, bool may) {
         const bool want = go && may;
         if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
@@ -1058,7 +1207,7 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
           float cr, cg, cb;
           colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
           float wk[NS];
-          sample_weights<NS>(g, c, ts, wk);
+          sample_weights<NS>(g, c, sp, wk);
 #pragma unroll
           for (int k = 0; k < NS; k++) {
             sg[k] += wk[k];
@@ -1067,7 +1216,8 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
             W2[k] = fmaf(wk[k], cb, W2[k]);
           }
         }
-      });
+      }); while (next_chunk(s, M, r, lane, n_active, go, a, b, win.z1, win, false, ls.error_flag,
+                            dummy_nodes, dummy_leaves, dummy_windows));
 
       // per-sample adjoints: dL/dsigma_k (into sg) and dL/dW_k (into W)
       const bool any = go && nhit > 0;
@@ -1075,7 +1225,7 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
 #pragma unroll
         for (int k = 0; k < NS; k++) {
           float dsig = 0.0f, dW = 0.0f;
-          if (ts[k] < tf && sg[k] > 0.0f) {
+          if (sp.t(k) < tf && sg[k] > 0.0f) {
             const float x = sg[k] * dt;
             const float E = exp_neg(x);
             const float rs = __builtin_amdgcn_rcpf(sg[k]);
@@ -1100,8 +1250,11 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
 
       // pass B: per-Gaussian adjoints, wave-reduced, one atomic per slot
       if (ballot(any) != 0) {
-        for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, lo, hi,
-                           ls.error_flag, [&](int j, bool may) {
+        // a chunked segment starts its chunks again for the lanes that hit
+        if (win.chunked)
+          next_chunk(s, M, r, lane, n_active, any, a, b, 0, win, false, ls.error_flag, dummy_nodes,
+                     dummy_leaves, dummy_windows);
+        do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j, bool may) {
           const bool want = any && may;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
@@ -1118,10 +1271,10 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
             float cr, cg, cb;
             colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
             float wk[NS];
-            sample_weights<NS>(g, c, ts, wk);
+            sample_weights<NS>(g, c, sp, wk);
 #pragma unroll
             for (int k = 0; k < NS; k++) {
-              const float u = ts[k] - c.ts;
+              const float u = sp.t(k) - c.ts;
               const float dw = sg[k] + W0[k] * cr + W1[k] * cg + W2[k] * cb;
               const float wdw = wk[k] * dw;
               ds += wdw;
@@ -1158,17 +1311,17 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
           const float mine = wave_reduce_slots(v, Y, dc0, dc1, dc2, lane);
           if (lane < 16 || (lane & 15) < op.sh_k)
             unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + lane, mine);
-        });
+        }); while (next_chunk(s, M, r, lane, n_active, any, a, b, win.z1, win, false, ls.error_flag,
+                              dummy_nodes, dummy_leaves, dummy_windows));
       }
 
       // restart after an empty segment: from the list inside the window, else
       // through the closest-hit traversal (same decisions as the forward)
       const bool empty = go && nhit == 0;
       float best = kInf;
-      if (op.ess && win.kind == SRC_LIST && ballot(empty)) {
+      if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r, lo, hi,
-                           ls.error_flag, [&](int j, bool may) {
+        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, [&](int j, bool may) {
           const bool want = empty && may;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
@@ -1177,7 +1330,6 @@ __global__ __launch_bounds__(kWave) void k_backward(SceneDev s, ViewTable vt, Ma
         });
       }
       if (go) step_after(op, grid, nhit > 0, best, tn, dS, b, ss);
-      if (win.kind == SRC_DFS) win.kind = SRC_LIST;
     }
   }
 }

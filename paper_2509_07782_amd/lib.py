@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("RGX_LIBRARY", os.path.join(HERE, "librgx.so"))
 RGX_OK = 0
 NSTAT = 10
 STAT_NAMES = ("Q", "P", "samples", "segments", "closest", "box_only", "nodes", "leaves",
-              "windows", "dfs_segments")
+              "windows", "chunked")
 
 
 class RgxError(RuntimeError):

@@ -45,11 +45,14 @@ def test_build_structure(torch_cuda):
     mu = sc["means"][perm[:na]].astype(np.float64)
     L = half[perm[:na]]
     assert np.all(aabb[:na, :3] <= mu - L + 1e-7) and np.all(aabb[:na, 3:] >= mu + L - 1e-7)
-    # walk the tree
+    # walk the tree; every node's stored leaf range is exactly the leaves below it
     seen = np.zeros(na, int)
-    stack = [(0, None)]
+    lo_hi = nodes[:, [11, 15]].copy().view(np.int32)
+    first = np.full(na - 1, na, int)
+    last = np.full(na - 1, -1, int)
+    stack = [(0, None, [])]
     while stack:
-        node, box = stack.pop()
+        node, box, path = stack.pop()
         nd = nodes[node]
         ch = nd[[3, 7]].view(np.int32)
         boxes = [np.r_[nd[0:3], nd[4:7]], np.r_[nd[8:11], nd[12:15]]]
@@ -60,9 +63,13 @@ def test_build_structure(torch_cuda):
                 leaf = ~c
                 seen[leaf] += 1
                 assert np.array_equal(b, aabb[leaf])
+                for a_ in path + [node]:
+                    first[a_] = min(first[a_], leaf)
+                    last[a_] = max(last[a_], leaf)
             else:
-                stack.append((c, b))
+                stack.append((c, b, path + [node]))
     assert np.all(seen == 1)
+    assert np.array_equal(lo_hi[:na - 1, 0], first) and np.array_equal(lo_hi[:na - 1, 1], last)
 
 
 def test_config1_brute_force_matches_oracle(torch_cuda):
