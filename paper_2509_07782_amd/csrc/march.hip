@@ -435,10 +435,13 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
 // every Gaussian whose chord meets some lane's window, with the 64-bit mask of
 // those lanes and the extreme chord ends over them, restricted to the Z-index
 // range [z0, z1).  The traversal is node-parallel: a FIFO frontier of
-// (node, ray mask, first leaf) lives in LDS and each round hands up to 64
-// frontier nodes to the 64 lanes, which load them independently and test both
-// child boxes against the rays of the node's mask.  Leaves are staged and
-// chord-tested 64 at a time.  When the frontier or the list would overflow,
+// (node, first leaf) lives in LDS and each round hands up to 64 frontier nodes
+// to the 64 lanes, which load them independently and test both child boxes
+// against the packet as a whole -- the bounding cone of the rays (apex at the
+// shared camera centre) and the shell between the nearest window start and
+// the farthest window end, a conservative test on the box's bounding sphere.
+// Leaves are staged and chord-tested against every ray, 64 leaves at a time,
+// which gives each list entry its exact ray mask and chord bounds.  When the frontier or the list would overflow,
 // z1 is lowered (a radix select over the pending Z indices) and everything at
 // or beyond it is dropped, so the result is always complete for [z0, z1);
 // the caller continues from z1 with another chunk.  The list is finally
@@ -454,9 +457,7 @@ struct WaveMem {
   union {
     struct {                       // during collection
       int32_t ring_id[kRingCap], ring_first[kRingCap];
-      uint32_t ring_mlo[kRingCap], ring_mhi[kRingCap];
       int32_t st_id[kStageCap];
-      uint32_t st_mlo[kStageCap], st_mhi[kStageCap];
     } c;
     uint64_t order[kListCap];      // afterwards: (Gaussian index << 32 | list slot), sorted
   } u;
@@ -547,18 +548,18 @@ __device__ __forceinline__ int compact_ring(WaveMem &M, int lane, int head, int 
     const int e = e0 + lane;
     const int slot = e & (kRingCap - 1);
     int id = 0, first = 0;
-    uint32_t mlo = 0, mhi = 0;
     bool keep = false;
     if (e < tail) {
-      id = M.u.c.ring_id[slot]; first = M.u.c.ring_first[slot];
-      mlo = M.u.c.ring_mlo[slot]; mhi = M.u.c.ring_mhi[slot];
+      id = M.u.c.ring_id[slot];
+      first = M.u.c.ring_first[slot];
       keep = first < z1;
     }
     __builtin_amdgcn_wave_barrier();
     const uint64_t b = ballot(keep);
     if (keep) {
       const int d = (base + __popcll(b & below)) & (kRingCap - 1);
-      M.u.c.ring_id[d] = id; M.u.c.ring_first[d] = first; M.u.c.ring_mlo[d] = mlo; M.u.c.ring_mhi[d] = mhi;
+      M.u.c.ring_id[d] = id;
+      M.u.c.ring_first[d] = first;
     }
     base += __popcll(b);
     __builtin_amdgcn_wave_barrier();
@@ -599,6 +600,71 @@ __device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int z1
   return valid;
 }
 
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return uniform_float(v);
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return uniform_float(v);
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return uniform_float(v);
+}
+
+// The packet bound: apex o, unit axis u, half-angle (cos, sin) padded
+// outward, and the depth shell [t_lo, t_hi] (distances from o).
+struct Cone {
+  float ux, uy, uz, cs, sn, t_lo, t_hi;
+  bool narrow;   // false: rays spread too far for the angular test
+};
+
+__device__ __forceinline__ Cone packet_cone(const WaveMem &M, const Ray &self, int lane,
+                                            uint64_t rays) {
+  const bool mine = (rays >> lane) & 1;
+  const float sx = wave_sum_f(mine ? self.dx : 0.0f), sy = wave_sum_f(mine ? self.dy : 0.0f),
+              sz = wave_sum_f(mine ? self.dz : 0.0f);
+  Cone k;
+  const float n2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+  const float inv = n2 > 0.0f ? rsqrtf(n2) : 0.0f;
+  k.ux = sx * inv; k.uy = sy * inv; k.uz = sz * inv;
+  // sine and cosine of each ray's angle to the axis (cross product: no
+  // cancellation at small angles)
+  const float cx = self.dy * k.uz - self.dz * k.uy, cy = self.dz * k.ux - self.dx * k.uz,
+              cz = self.dx * k.uy - self.dy * k.ux;
+  const float sn = wave_max(mine ? sqrtf(fmaf(cx, cx, fmaf(cy, cy, cz * cz))) : 0.0f);
+  const float cs = wave_min(mine ? fmaf(self.dx, k.ux, fmaf(self.dy, k.uy, self.dz * k.uz)) : 1.0f);
+  k.narrow = n2 > 0.0f && cs > 0.5f;
+  k.sn = fminf(sn * 1.0001f + 2e-6f, 1.0f);
+  k.cs = sqrtf(fmaxf(1.0f - k.sn * k.sn, 0.0f));
+  k.t_lo = wave_min(mine ? M.rlo[lane] : kInf);
+  k.t_hi = wave_max(mine ? M.rhi[lane] : -kInf);
+  return k;
+}
+
+// Conservative: false only if no point of the box lies on a ray of the
+// packet at a depth inside the shell.
+__device__ __forceinline__ bool cone_box(const Cone &k, const Ray &o, float lx, float ly, float lz,
+                                         float hx, float hy, float hz) {
+  const float vx = fmaf(0.5f, lx + hx, -o.ox), vy = fmaf(0.5f, ly + hy, -o.oy),
+              vz = fmaf(0.5f, lz + hz, -o.oz);
+  const float ex = 0.5f * (hx - lx), ey = 0.5f * (hy - ly), ez = 0.5f * (hz - lz);
+  const float rho = fmaf(sqrtf(fmaf(ex, ex, fmaf(ey, ey, ez * ez))), 1.0001f, 1e-6f);
+  const float d = sqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+  const float pad = fmaf(d, 2e-6f, rho);
+  if (d - pad > k.t_hi || d + pad < k.t_lo) return false;
+  const float al = fmaf(vx, k.ux, fmaf(vy, k.uy, vz * k.uz));
+  if (al + pad < 0.0f) return false;
+  if (!k.narrow) return true;
+  const float wx = vy * k.uz - vz * k.uy, wy = vz * k.ux - vx * k.uz, wz = vx * k.uy - vy * k.ux;
+  const float perp = sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz)));
+  return fmaf(perp, k.cs, -al * k.sn) <= pad;
+}
+
 // Collects the list for the rays in `rays` (windows in M.rlo / M.rhi) and
 // the Z range [z0, z1); z1 may be lowered.  Returns the number of list
 // entries, or -1 on a malformed tree (error flag set).
@@ -611,21 +677,18 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
   if (lane == 0) {
     M.u.c.ring_id[0] = 0;
     M.u.c.ring_first[0] = 0;
-    M.u.c.ring_mlo[0] = (uint32_t)rays;
-    M.u.c.ring_mhi[0] = (uint32_t)(rays >> 32);
   }
+  const Cone cone = packet_cone(M, self, lane, rays);
   const uint64_t below = lanes_below(lane);
   for (;;) {
     __builtin_amdgcn_wave_barrier();
     const int n = min(min(64, tail - head), (kStageCap - staged) >> 1);
     if (n > 0) {
       int id = 0;
-      uint64_t mk = 0;
       bool live = false;
       if (lane < n) {
         const int slot = (head + lane) & (kRingCap - 1);
         id = M.u.c.ring_id[slot];
-        mk = join64(M.u.c.ring_mlo[slot], M.u.c.ring_mhi[slot]);
         live = M.u.c.ring_first[slot] < z1;      // else cut off by a later z1
       }
       head += n;
@@ -647,19 +710,11 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       if (ballot(bad)) { if (err) *err = 3; return -1; }
       const bool inL = live && nlo < z1 && gamma >= z0;
       const bool inR = live && cr != kNoChild && gamma + 1 < z1 && nhi >= z0;
-      uint64_t mL = 0, mR = 0;
-      for (uint64_t rem = rays; rem; rem &= rem - 1) {
-        const int r = __builtin_ctzll(rem);
-        const Ray q = lds_ray(M, self, r);
-        const float lo = M.rlo[r], hi = M.rhi[r];
-        if ((mk >> r) & 1) {
-          if (inL && box_hit(a.x, a.y, a.z, b.x, b.y, b.z, q, lo, hi)) mL |= 1ull << r;
-          if (inR && box_hit(c.x, c.y, c.z, d.x, d.y, d.z, q, lo, hi)) mR |= 1ull << r;
-        }
-      }
+      const bool hL = inL && cone_box(cone, self, a.x, a.y, a.z, b.x, b.y, b.z);
+      const bool hR = inR && cone_box(cone, self, c.x, c.y, c.z, d.x, d.y, d.z);
       // children, in lane order, left before right
-      bool lI = mL != 0 && cl >= 0, rI = mR != 0 && cr >= 0;
-      bool lL = mL != 0 && cl < 0, rL = mR != 0 && cr < 0;
+      bool lI = hL && cl >= 0, rI = hR && cr >= 0;
+      bool lL = hL && cl < 0, rL = hR && cr < 0;
       {
         int tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
         if (tail + tot - head > kRingCap) {
@@ -687,14 +742,14 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         int pos = tail + __popcll(b1 & below) + __popcll(b2 & below);
         if (lI) {
           const int slot = pos & (kRingCap - 1);
-          M.u.c.ring_id[slot] = cl; M.u.c.ring_first[slot] = nlo;
-          M.u.c.ring_mlo[slot] = (uint32_t)mL; M.u.c.ring_mhi[slot] = (uint32_t)(mL >> 32);
+          M.u.c.ring_id[slot] = cl;
+          M.u.c.ring_first[slot] = nlo;
           pos++;
         }
         if (rI) {
           const int slot = pos & (kRingCap - 1);
-          M.u.c.ring_id[slot] = cr; M.u.c.ring_first[slot] = gamma + 1;
-          M.u.c.ring_mlo[slot] = (uint32_t)mR; M.u.c.ring_mhi[slot] = (uint32_t)(mR >> 32);
+          M.u.c.ring_id[slot] = cr;
+          M.u.c.ring_first[slot] = gamma + 1;
         }
         tail += tot;
       }
@@ -702,8 +757,8 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         const uint64_t b1 = ballot(lL || rL), b2 = ballot(lL && rL);
         const int tot = __popcll(b1) + __popcll(b2);
         int pos = staged + __popcll(b1 & below) + __popcll(b2 & below);
-        if (lL) { M.u.c.st_id[pos] = ~cl; M.u.c.st_mlo[pos] = (uint32_t)mL; M.u.c.st_mhi[pos] = (uint32_t)(mL >> 32); pos++; }
-        if (rL) { M.u.c.st_id[pos] = ~cr; M.u.c.st_mlo[pos] = (uint32_t)mR; M.u.c.st_mhi[pos] = (uint32_t)(mR >> 32); }
+        if (lL) M.u.c.st_id[pos++] = ~cl;
+        if (rL) M.u.c.st_id[pos] = ~cr;
         staged += tot;
       }
     }
@@ -713,25 +768,26 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       __builtin_amdgcn_wave_barrier();
       const int k = min(64, staged);
       int j = 0;
-      uint64_t mk = 0;
+      bool test = false;
       if (lane < k) {
         j = M.u.c.st_id[lane];
-        mk = j < z1 ? join64(M.u.c.st_mlo[lane], M.u.c.st_mhi[lane]) : 0ull;
+        test = j < z1;
       }
       uint64_t hitm = 0;
       float tmin = kInf, tmax = -kInf;
-      if (mk != 0) {
-        const Gauss g = load_gauss_lane(s.geom, j);
-        for (uint64_t rem = mk; rem; rem &= rem - 1) {
+      if (ballot(test)) {
+        const Gauss g = load_gauss_lane(s.geom, test ? j : 0);
+        const float *bx = s.aabb + 6 * (size_t)(test ? j : 0);
+        for (uint64_t rem = rays; rem; rem &= rem - 1) {
           const int r = __builtin_ctzll(rem);
           const Ray q = lds_ray(M, self, r);
           const float lo = M.rlo[r], hi = M.rhi[r];
           const Chord ch = chord(g, q);
-          if (ch.exists && ch.tin <= hi && ch.tout >= lo) {
+          if (test && ch.exists && ch.tin <= hi && ch.tout >= lo) {
             hitm |= 1ull << r;
             tmin = fminf(tmin, ch.tin);
             tmax = fmaxf(tmax, ch.tout);
-          } else if (stats) {
+          } else if (stats && test && box_hit(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], q, lo, hi)) {
             atomicAdd(&M.cnt_box[r], 1);
           }
         }
@@ -769,15 +825,14 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       // move the remaining staged entries to the front
       const int rest = staged - k;
       int rid[2];
-      uint32_t rlo2[2], rhi2[2];
       for (int e = 0; e < 2; e++) {
         const int src = k + lane + 64 * e;
-        if (lane + 64 * e < rest) { rid[e] = M.u.c.st_id[src]; rlo2[e] = M.u.c.st_mlo[src]; rhi2[e] = M.u.c.st_mhi[src]; }
+        if (lane + 64 * e < rest) rid[e] = M.u.c.st_id[src];
       }
       __builtin_amdgcn_wave_barrier();
       for (int e = 0; e < 2; e++) {
         const int dst = lane + 64 * e;
-        if (dst < rest) { M.u.c.st_id[dst] = rid[e]; M.u.c.st_mlo[dst] = rlo2[e]; M.u.c.st_mhi[dst] = rhi2[e]; }
+        if (dst < rest) M.u.c.st_id[dst] = rid[e];
       }
       staged = rest;
     }
@@ -825,17 +880,6 @@ __device__ __forceinline__ void for_each_candidate(int kind, const WaveMem &M, i
   } else {
     for (int e = 0; e < n_active; e++) fn(e, true);
   }
-}
-
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return uniform_float(v);
-}
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return uniform_float(v);
 }
 
 // Per-wave window bookkeeping shared by forward and backward.
