@@ -121,7 +121,12 @@ enum {
   RGX_STAT_LEAVES,       /* leaves the wave visited for the segment collections */
   RGX_STAT_WINDOWS,      /* window collections the wave made (attempts included) */
   RGX_STAT_CHUNKED,      /* segments whose candidates were collected in several Z chunks */
-  RGX_NSTAT = 10
+  RGX_STAT_CAND,         /* per wave: candidates evaluated (some lane may hit them) */
+  RGX_STAT_CAND_HIT,     /* per wave: candidates that some lane hit */
+  RGX_STAT_KCYC_COLLECT, /* per wave: shader-clock kilocycles in window collection */
+  RGX_STAT_KCYC_CLOSEST, /* per wave: kilocycles in closest-hit queries */
+  RGX_STAT_KCYC_TILE,    /* per wave: kilocycles for the whole tile */
+  RGX_NSTAT = 15
 };
 
 /* Create / destroy a context on HIP device `device`.  rgx_create allocates. */

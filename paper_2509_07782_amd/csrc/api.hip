@@ -20,7 +20,8 @@ static_assert(RGX_STAT_Q == ST_Q && RGX_STAT_P == ST_P && RGX_STAT_SAMPLES == ST
                   RGX_STAT_SEGMENTS == ST_SEGMENTS && RGX_STAT_CLOSEST == ST_CLOSEST &&
                   RGX_STAT_BOX_ONLY == ST_BOX_ONLY && RGX_STAT_NODES == ST_NODES &&
                   RGX_STAT_LEAVES == ST_LEAVES && RGX_STAT_WINDOWS == ST_WINDOWS &&
-                  RGX_STAT_CHUNKED == ST_CHUNKED && RGX_NSTAT == kNStat,
+                  RGX_STAT_CHUNKED == ST_CHUNKED && RGX_STAT_KCYC_TILE == ST_KCYC_TILE &&
+                  RGX_NSTAT == kNStat,
               "stat slots");
 
 namespace {

@@ -90,6 +90,9 @@ __global__ __launch_bounds__(256) void k_preprocess(int64_t n, const float *__re
         lo[r] = mu[r] - L;
         hi[r] = mu[r] + L;
       }
+      // bounding sphere of the ellipsoid: radius k max(s), padded like L
+      float rad = k * fmaxf(s[0], fmaxf(s[1], s[2]));
+      g[G_RAD] = rad * 1.0001f + 2e-6f * (amax + rad) + 1e-30f;
       atomicMin(&sb[0], f2ord(mu[0])); atomicMin(&sb[1], f2ord(mu[1])); atomicMin(&sb[2], f2ord(mu[2]));
       atomicMax(&sb[3], f2ord(mu[0])); atomicMax(&sb[4], f2ord(mu[1])); atomicMax(&sb[5], f2ord(mu[2]));
       atomicAdd(&scount, 1);

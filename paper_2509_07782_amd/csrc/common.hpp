@@ -16,13 +16,15 @@ constexpr int32_t kNoChild = INT32_MIN;
 
 // Packed geometry record, Z order: [mu.xyz, k^2, M (3x3 row-major), sigma~, log2 sigma~, pad]
 // with M = S^-1 R^T so that q = |M (x - mu)|^2.
-enum GeomSlot { G_MU = 0, G_K2 = 3, G_M = 4, G_SIG = 13, G_L2SIG = 14 };
+// G_RAD: radius of a sphere around the mean holding the whole ellipsoid
+enum GeomSlot { G_MU = 0, G_K2 = 3, G_M = 4, G_SIG = 13, G_L2SIG = 14, G_RAD = 15 };
 
 // per-ray statistics slots (same order as the public RGX_STAT_* enum)
 enum { ST_Q = 0, ST_P, ST_SAMPLES, ST_SEGMENTS, ST_CLOSEST, ST_BOX_ONLY, ST_NODES, ST_LEAVES,
-       ST_WINDOWS, ST_CHUNKED };
-constexpr int kNStatUsed = 10;
-constexpr int kNStat = 10;
+       ST_WINDOWS, ST_CHUNKED, ST_CAND, ST_CAND_HIT, ST_KCYC_COLLECT, ST_KCYC_CLOSEST,
+       ST_KCYC_TILE };
+constexpr int kNStatUsed = 15;
+constexpr int kNStat = 15;
 
 struct View {
   const int32_t *tile_order;  // tile coordinates (tx | ty << 16) in launch order

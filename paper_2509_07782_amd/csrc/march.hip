@@ -3,30 +3,25 @@
 //
 // Execution model: one wave64 (one workgroup) owns one tile of 64 rays.  Each
 // lane marches its ray segment by segment (Alg. 1).  Candidate Gaussians come
-// from a per-wave window list: for a depth window covering several segments of
-// every live lane, a node-parallel walk of the LBVH gathers the Gaussians
-// whose ellipsoid chord meets some lane's window, each with the mask of those
-// lanes and its extreme chord ends (see collect_window).  Every segment then
-// runs over that list with a wave-uniform depth pre-check, so one BVH walk
-// serves several segments and its memory latency is spread over 64
-// independent node fetches per round.  Geometry and colour records of the
-// Gaussian being evaluated are read at wave-uniform addresses through the
-// scalar cache.  Closest-hit restarts beyond the window use a depth-first
-// packet traversal.
+// from a per-wave window list: for a depth window covering one or more
+// segments of every live lane, a node-parallel walk of the LBVH gathers the
+// Gaussians whose ellipsoid chord meets some lane's window, each with the
+// mask of those lanes and its extreme chord ends (see collect_window).  Every
+// segment then runs over that list with a wave-uniform depth pre-check, so
+// one BVH walk serves several segments and its memory latency is spread over
+// 64 independent node fetches per round.  A window too large for the list is
+// cut by Z index and the segment proceeds chunk by chunk.  Geometry and colour
+// records of the Gaussian being evaluated are read at wave-uniform addresses
+// through the scalar cache.  Closest-hit restarts beyond the window use a
+// depth-first packet traversal, nearer child first.
 //
-// Every ray meets its Gaussians in Z-index order (the window list is sorted,
-// the depth-first walk visits leaves left to right, brute force counts up),
-// whatever packet, window, tile shape or ray order is used; the images of all
-// these variants are therefore bit-identical.
+// Every ray meets its Gaussians in Z-index order (window lists and their
+// chunks are sorted, brute force counts up), whatever packet, window, tile
+// shape or ray order is used; the images of all these variants are
+// therefore bit-identical.
 #include "common.hpp"
 #include "internal.hpp"
 
-#ifndef RGX_NODE_VLOAD
-#define RGX_NODE_VLOAD 0
-#endif
-#ifndef RGX_REC_VLOAD
-#define RGX_REC_VLOAD 0
-#endif
 
 namespace rgx {
 
@@ -58,6 +53,21 @@ __device__ __forceinline__ bool box_hit(float lx, float ly, float lz, float hx, 
   return fmaxf(bmin, lo) <= fminf(bmax, hi);
 }
 
+// Entry parameter of the box over [lo, hi] (same slab arithmetic as box_hit),
+// or +inf when the box misses the interval.
+__device__ __forceinline__ float box_entry(float lx, float ly, float lz, float hx, float hy,
+                                           float hz, const Ray &r, float lo, float hi) {
+  const float tx0 = (lx - r.ox) * r.ix, tx1 = (hx - r.ox) * r.ix;
+  const float ty0 = (ly - r.oy) * r.iy, ty1 = (hy - r.oy) * r.iy;
+  const float tz0 = (lz - r.oz) * r.iz, tz1 = (hz - r.oz) * r.iz;
+  float bmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
+  float bmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+  bmin = fmaf(-fabsf(bmin), 1e-6f, bmin);
+  bmax = fmaf(fabsf(bmax), 1e-6f, bmax);
+  const float e = fmaxf(bmin, lo);
+  return e <= fminf(bmax, hi) ? e : kInf;
+}
+
 // Geometry of one Gaussian (wave-uniform, from the scalar cache).
 struct Gauss {
   float mx, my, mz, k2;
@@ -65,20 +75,8 @@ struct Gauss {
   float sig, l2sig;
 };
 
-// Uniform zero held in a VGPR: an address offset by it is loaded through the
-// vector memory path (L1/TA) instead of the scalar cache.
-__device__ __forceinline__ int vgpr_zero() {
-  int z = 0;
-  asm volatile("" : "+v"(z));
-  return z;
-}
-
 __device__ __forceinline__ Gauss load_gauss(const float *geom, int j) {
-#if RGX_REC_VLOAD
-  const vf4 *p = reinterpret_cast<const vf4 *>(geom) + 4 * j + vgpr_zero();
-#else
   cfloat4p p = as_const4(geom) + 4 * j;
-#endif
   const vf4 a = p[0], b = p[1], c = p[2], d = p[3];
   Gauss g;
   g.mx = a.x; g.my = a.y; g.mz = a.z; g.k2 = a.w;
@@ -156,62 +154,6 @@ struct WaveStack {
   __device__ __forceinline__ int pop() {
     sp--;
     return sp < 64 ? __builtin_amdgcn_readlane(s0, sp) : __builtin_amdgcn_readlane(s1, sp - 64);
-  }
-};
-
-// Packet traversal in left-to-right leaf order, as an iterator: next() returns
-// the next leaf (wave-uniform) whose box meets some active lane's interval
-// [lo, hi], or -1.  A left leaf is returned at once and the right child waits
-// on the stack, so leaves come out in Z order whatever the packet prunes.
-// Brute force enumerates every active Gaussian in the same order.
-struct LeafIter {
-  WaveStack st;
-  int node, visits, n_inner, n_active, next_brute;
-  bool brute;
-  __device__ __forceinline__ void init(int n_act, bool brute_force) {
-    st.lane = __lane_id();
-    st.sp = 0;
-    n_active = n_act;
-    n_inner = n_act > 1 ? n_act - 1 : 1;
-    node = n_act > 0 ? 0 : -1;
-    visits = 0;
-    brute = brute_force;
-    next_brute = 0;
-  }
-  __device__ __forceinline__ int next(const SceneDev &s, const Ray &r, float lo, float hi,
-                                      int32_t *err) {
-    if (brute) return next_brute < n_active ? next_brute++ : -1;
-    for (;;) {
-      if (node < 0) {
-        if (st.sp == 0) return -1;
-        const int v = st.pop();
-        if (v < 0) return ~v;
-        node = v;
-      }
-      // a valid tree loads each of its n_inner nodes at most once
-      if (++visits > n_inner) { if (err) *err = 2; st.sp = 0; node = -1; return -1; }
-#if RGX_NODE_VLOAD
-      const vf4 *np = reinterpret_cast<const vf4 *>(s.nodes) + 4 * node + vgpr_zero();
-      const vf4 a = np[0], b = np[1], c = np[2], d = np[3];
-      const int cl = uniform_int(__float_as_int(a.w)), cr = uniform_int(__float_as_int(b.w));
-#else
-      cfloat4p np = as_const4(s.nodes) + 4 * node;
-      const vf4 a = np[0], b = np[1], c = np[2], d = np[3];
-      const int cl = __float_as_int(a.w), cr = __float_as_int(b.w);
-#endif
-      const bool bad = (cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
-                       (cr != kNoChild && (cr >= 0 ? cr >= n_inner : ~cr >= n_active));
-      if (bad) { if (err) *err = 3; st.sp = 0; node = -1; return -1; }
-      const bool hl = ballot(box_hit(a.x, a.y, a.z, b.x, b.y, b.z, r, lo, hi)) != 0;
-      const bool hr = cr != kNoChild && ballot(box_hit(c.x, c.y, c.z, d.x, d.y, d.z, r, lo, hi)) != 0;
-      if (hr && !st.push(cr)) { if (err) *err = 1; st.sp = 0; node = -1; return -1; }
-      if (hl) {
-        if (cl >= 0) { node = cl; continue; }
-        node = -1;
-        return ~cl;
-      }
-      node = -1;
-    }
   }
 };
 
@@ -402,9 +344,27 @@ __device__ __forceinline__ float wave_reduce_slots(const float *g, const float *
   return x[0];
 }
 
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return uniform_float(v);
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return uniform_float(v);
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return uniform_float(v);
+}
+
 // Closest hit (Alg. 1 ClosestHit, Eq. 4) for the lanes with `pending` set:
 // min over Gaussians whose chord meets [cl_lo, t_far] of max(t_in, cl_lo).
-// Depth-first packet traversal; the shrinking per-lane bound prunes.
+// Depth-first packet traversal, nearer child first (by the smallest entry
+// over the wave's pending lanes); each lane's bound shrinks to its best hit
+// so far and prunes.  A minimum does not depend on the visiting order.
 __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts &op, int n_active,
                                              const Ray &r, float tn, float tf, float dS,
                                              SegState &ss, int32_t *err, int32_t *st_closest) {
@@ -412,14 +372,46 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
   const float lo = ss.pending ? ss.cl_lo : kInf;
   float hi = ss.pending ? tf : -kInf;
   float best = kInf;
-  LeafIter it;
-  it.init(n_active, op.brute_force);
-  for (int j; (j = it.next(s, r, lo, hi, err)) >= 0;) {
+  auto leaf = [&](int j) {
     const Gauss g = load_gauss(s.geom, j);
     const Chord c = chord(g, r);
     if (c.exists && c.tin <= hi && c.tout >= lo) {
       best = fminf(best, fmaxf(c.tin, lo));
       hi = fminf(hi, best);
+    }
+  };
+  if (op.brute_force) {
+    for (int j = 0; j < n_active; j++) leaf(j);
+  } else if (n_active > 0) {
+    const int n_inner = n_active > 1 ? n_active - 1 : 1;
+    WaveStack st;
+    st.lane = __lane_id();
+    st.sp = 0;
+    int node = 0, visits = 0;
+    for (;;) {
+      if (node < 0) {
+        if (st.sp == 0) break;
+        const int v = st.pop();
+        if (v < 0) { leaf(~v); continue; }
+        node = v;
+      }
+      if (++visits > n_inner) { if (err) *err = 2; break; }
+      cfloat4p np = as_const4(s.nodes) + 4 * node;
+      const vf4 a = np[0], b = np[1], c = np[2], d = np[3];
+      const int cl = __float_as_int(a.w), cr = __float_as_int(b.w);
+      const bool bad = (cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
+                       (cr != kNoChild && (cr >= 0 ? cr >= n_inner : ~cr >= n_active));
+      if (bad) { if (err) *err = 3; break; }
+      const float el = wave_min(box_entry(a.x, a.y, a.z, b.x, b.y, b.z, r, lo, hi));
+      const float er = cr != kNoChild ? wave_min(box_entry(c.x, c.y, c.z, d.x, d.y, d.z, r, lo, hi))
+                                      : kInf;
+      const bool hl = el < kInf, hr = er < kInf;
+      if (!hl && !hr) { node = -1; continue; }
+      int near = cl, far = cr;
+      if (hr && (!hl || er < el)) { near = cr; far = cl; }
+      if (hl && hr && !st.push(far)) { if (err) *err = 1; break; }
+      if (near >= 0) node = near;
+      else { leaf(~near); node = -1; }
     }
   }
   if (ss.pending) {
@@ -432,25 +424,25 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
 
 // ---------------------------------------------------------------------------
 // Window collection.  For a per-lane depth window [lo, hi] the wave gathers
-// every Gaussian whose chord meets some lane's window, with the 64-bit mask of
-// those lanes and the extreme chord ends over them, restricted to the Z-index
-// range [z0, z1).  The traversal is node-parallel: a FIFO frontier of
-// (node, first leaf) lives in LDS and each round hands up to 64 frontier nodes
-// to the 64 lanes, which load them independently and test both child boxes
-// against the packet as a whole -- the bounding cone of the rays (apex at the
+// every Gaussian that may meet some lane's window, restricted to the Z-index
+// range [z0, z1), with a conservative depth interval for each.  Every test is
+// against the packet as a whole: the bounding cone of the rays (apex at the
 // shared camera centre) and the shell between the nearest window start and
-// the farthest window end, a conservative test on the box's bounding sphere.
-// Leaves are staged and chord-tested against every ray, 64 leaves at a time,
-// which gives each list entry its exact ray mask and chord bounds.  When the frontier or the list would overflow,
-// z1 is lowered (a radix select over the pending Z indices) and everything at
-// or beyond it is dropped, so the result is always complete for [z0, z1);
-// the caller continues from z1 with another chunk.  The list is finally
-// sorted by Z index, so every ray meets its Gaussians in Z order whatever
-// window, chunking or packet produced the list -- the order of brute force.
+// the farthest window end, applied to bounding spheres (of a node's child
+// boxes, of a leaf's ellipsoid).  Exact per-ray chords are left to the
+// segment loop, which computes them anyway.  The traversal is node-parallel:
+// a FIFO frontier of (node, first leaf) lives in LDS and each round hands up
+// to 64 frontier nodes to the 64 lanes, which load them independently.  When
+// the frontier or the list would overflow, z1 is lowered (a radix select over
+// the pending Z indices) and everything at or beyond it is dropped, so the
+// result is always complete for [z0, z1); the caller continues from z1 with
+// another chunk.  The list is finally sorted by Z index, so every ray meets
+// its Gaussians in Z order whatever window, chunking or packet produced the
+// list -- the order of brute force.
 
-constexpr int kRingCap = 256;    // frontier entries (power of two)
+constexpr int kRingCap = 512;    // frontier entries (power of two)
 constexpr int kStageCap = 160;   // staged leaves; a round adds at most 2 per node
-constexpr int kListCap = 256;    // window list entries (LDS budget: 3 waves per SIMD)
+constexpr int kListCap = 512;    // window list entries (power of two; bitonic sort)
 
 struct WaveMem {
   float rdx[64], rdy[64], rdz[64], rix[64], riy[64], riz[64], rlo[64], rhi[64];
@@ -462,14 +454,9 @@ struct WaveMem {
     uint64_t order[kListCap];      // afterwards: (Gaussian index << 32 | list slot), sorted
   } u;
   int32_t l_id[kListCap];
-  uint32_t l_mlo[kListCap], l_mhi[kListCap];
   float l_tin[kListCap], l_tout[kListCap];
   int32_t cnt_box[64];             // per-ray AABB-only leaf count (statistics)
 };
-
-__device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) {
-  return (uint64_t)lo | ((uint64_t)hi << 32);
-}
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -520,18 +507,21 @@ __device__ __forceinline__ int compact_list(WaveMem &M, int lane, int count, int
   for (int e0 = 0; e0 < count; e0 += 64) {
     const int e = e0 + lane;
     int id = 0;
-    uint32_t mlo = 0, mhi = 0;
     float tin = 0.0f, tout = 0.0f;
     bool keep = false;
     if (e < count) {
-      id = M.l_id[e]; mlo = M.l_mlo[e]; mhi = M.l_mhi[e]; tin = M.l_tin[e]; tout = M.l_tout[e];
+      id = M.l_id[e];
+      tin = M.l_tin[e];
+      tout = M.l_tout[e];
       keep = id < z1;
     }
     __builtin_amdgcn_wave_barrier();
     const uint64_t b = ballot(keep);
     if (keep) {
       const int pos = base + __popcll(b & below);
-      M.l_id[pos] = id; M.l_mlo[pos] = mlo; M.l_mhi[pos] = mhi; M.l_tin[pos] = tin; M.l_tout[pos] = tout;
+      M.l_id[pos] = id;
+      M.l_tin[pos] = tin;
+      M.l_tout[pos] = tout;
     }
     base += __popcll(b);
     __builtin_amdgcn_wave_barrier();
@@ -600,21 +590,6 @@ __device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int z1
   return valid;
 }
 
-__device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return uniform_float(v);
-}
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return uniform_float(v);
-}
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return uniform_float(v);
-}
 
 // The packet bound: apex o, unit axis u, half-angle (cos, sin) padded
 // outward, and the depth shell [t_lo, t_hi] (distances from o).
@@ -646,23 +621,32 @@ __device__ __forceinline__ Cone packet_cone(const WaveMem &M, const Ray &self, i
   return k;
 }
 
-// Conservative: false only if no point of the box lies on a ray of the
-// packet at a depth inside the shell.
-__device__ __forceinline__ bool cone_box(const Cone &k, const Ray &o, float lx, float ly, float lz,
-                                         float hx, float hy, float hz) {
-  const float vx = fmaf(0.5f, lx + hx, -o.ox), vy = fmaf(0.5f, ly + hy, -o.oy),
-              vz = fmaf(0.5f, lz + hz, -o.oz);
-  const float ex = 0.5f * (hx - lx), ey = 0.5f * (hy - ly), ez = 0.5f * (hz - lz);
-  const float rho = fmaf(sqrtf(fmaf(ex, ex, fmaf(ey, ey, ez * ez))), 1.0001f, 1e-6f);
+// Conservative: false only if no point of the sphere (centre v relative to
+// the apex, radius rho) lies on a ray of the packet at a depth inside the
+// shell.  On true, [*dlo, *dhi] bounds the depth of every such point.
+__device__ __forceinline__ bool cone_sphere(const Cone &k, float vx, float vy, float vz, float rho,
+                                            float *dlo, float *dhi) {
   const float d = sqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
-  const float pad = fmaf(d, 2e-6f, rho);
-  if (d - pad > k.t_hi || d + pad < k.t_lo) return false;
+  // rho's margin covers the FP32 chord ends near tangency (~3e-4 of the extent)
+  const float pad = fmaf(d, 1e-5f, rho * 1.001f);
+  *dlo = d - pad;
+  *dhi = d + pad;
+  if (*dlo > k.t_hi || *dhi < k.t_lo) return false;
   const float al = fmaf(vx, k.ux, fmaf(vy, k.uy, vz * k.uz));
   if (al + pad < 0.0f) return false;
   if (!k.narrow) return true;
   const float wx = vy * k.uz - vz * k.uy, wy = vz * k.ux - vx * k.uz, wz = vx * k.uy - vy * k.ux;
   const float perp = sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz)));
   return fmaf(perp, k.cs, -al * k.sn) <= pad;
+}
+
+__device__ __forceinline__ bool cone_box(const Cone &k, const Ray &o, float lx, float ly, float lz,
+                                         float hx, float hy, float hz) {
+  const float ex = 0.5f * (hx - lx), ey = 0.5f * (hy - ly), ez = 0.5f * (hz - lz);
+  float dlo, dhi;
+  return cone_sphere(k, fmaf(0.5f, lx + hx, -o.ox), fmaf(0.5f, ly + hy, -o.oy),
+                     fmaf(0.5f, lz + hz, -o.oz), sqrtf(fmaf(ex, ex, fmaf(ey, ey, ez * ez))), &dlo,
+                     &dhi);
 }
 
 // Collects the list for the rays in `rays` (windows in M.rlo / M.rhi) and
@@ -714,28 +698,26 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       const bool hR = inR && cone_box(cone, self, c.x, c.y, c.z, d.x, d.y, d.z);
       // children, in lane order, left before right
       bool lI = hL && cl >= 0, rI = hR && cr >= 0;
-      bool lL = hL && cl < 0, rL = hR && cr < 0;
+      const bool lL = hL && cl < 0, rL = hR && cr < 0;
       {
         int tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
         if (tail + tot - head > kRingCap) {
-          // frontier overflow: lower z1 to half the pending subtrees
-          int v[6];
-          bool ok[6];
+          // frontier overflow: lower z1 to keep half the pending subtrees
+          int v[kRingCap / 64 + 2];
+          bool ok[kRingCap / 64 + 2];
           const int pend = tail - head;
 #pragma unroll
-          for (int k = 0; k < 4; k++) {
+          for (int k = 0; k < kRingCap / 64; k++) {
             const int e = lane + 64 * k;
             ok[k] = e < pend;
             v[k] = ok[k] ? M.u.c.ring_first[(head + e) & (kRingCap - 1)] : 0;
           }
-          v[4] = nlo; ok[4] = lI;
-          v[5] = gamma + 1; ok[5] = rI;
+          v[kRingCap / 64] = nlo; ok[kRingCap / 64] = lI;
+          v[kRingCap / 64 + 1] = gamma + 1; ok[kRingCap / 64 + 1] = rI;
           z1 = select_cut(v, ok, z0 + 1, z1, kRingCap / 2);
           tail = compact_ring(M, lane, head, tail, z1);
           lI = lI && nlo < z1;
           rI = rI && gamma + 1 < z1;
-          lL = lL && gamma < z1;
-          rL = rL && gamma + 1 < z1;
           tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
         }
         const uint64_t b1 = ballot(lI || rI), b2 = ballot(lI && rI);
@@ -754,6 +736,7 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         tail += tot;
       }
       {
+        // leaves past a lowered z1 are filtered when tested
         const uint64_t b1 = ballot(lL || rL), b2 = ballot(lL && rL);
         const int tot = __popcll(b1) + __popcll(b2);
         int pos = staged + __popcll(b1 & below) + __popcll(b2 & below);
@@ -763,7 +746,8 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       }
     }
     const bool done = head == tail;
-    // chord tests of staged leaves, 64 at a time, in staging order
+    // tests of staged leaves, 64 at a time, in staging order: the bounding
+    // sphere of the ellipsoid against the packet gives the entry's depth bounds
     while (staged >= 64 || (done && staged > 0)) {
       __builtin_amdgcn_wave_barrier();
       const int k = min(64, staged);
@@ -773,27 +757,28 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         j = M.u.c.st_id[lane];
         test = j < z1;
       }
-      uint64_t hitm = 0;
-      float tmin = kInf, tmax = -kInf;
-      if (ballot(test)) {
+      bool keep = false;
+      float tmin = 0.0f, tmax = 0.0f;
+      if (test) {
+        const vf4 *gp = reinterpret_cast<const vf4 *>(s.geom) + 4 * j;
+        const vf4 g0 = gp[0], g3 = gp[3];
+        keep = cone_sphere(cone, g0.x - self.ox, g0.y - self.oy, g0.z - self.oz, g3.w, &tmin,
+                           &tmax);
+      }
+      if (stats && ballot(test)) {
+        // statistics only: AABB-only leaves per ray (box met, ellipsoid missed)
         const Gauss g = load_gauss_lane(s.geom, test ? j : 0);
         const float *bx = s.aabb + 6 * (size_t)(test ? j : 0);
         for (uint64_t rem = rays; rem; rem &= rem - 1) {
           const int r = __builtin_ctzll(rem);
           const Ray q = lds_ray(M, self, r);
           const float lo = M.rlo[r], hi = M.rhi[r];
+          if (!test || !box_hit(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], q, lo, hi)) continue;
           const Chord ch = chord(g, q);
-          if (test && ch.exists && ch.tin <= hi && ch.tout >= lo) {
-            hitm |= 1ull << r;
-            tmin = fminf(tmin, ch.tin);
-            tmax = fmaxf(tmax, ch.tout);
-          } else if (stats && test && box_hit(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], q, lo, hi)) {
-            atomicAdd(&M.cnt_box[r], 1);
-          }
+          if (!(ch.exists && ch.tin <= hi && ch.tout >= lo)) atomicAdd(&M.cnt_box[r], 1);
         }
       }
       leaves_out += k;
-      bool keep = hitm != 0;
       int tot = __popcll(ballot(keep));
       if (count + tot > kListCap) {
         // list overflow: lower z1 so that half the list remains
@@ -816,8 +801,6 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       if (keep) {
         const int pos = count + __popcll(bk & below);
         M.l_id[pos] = j;
-        M.l_mlo[pos] = (uint32_t)hitm;
-        M.l_mhi[pos] = (uint32_t)(hitm >> 32);
         M.l_tin[pos] = tmin;
         M.l_tout[pos] = tmax;
       }
@@ -848,37 +831,29 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
 
 enum SourceKind { SRC_LIST = 0, SRC_BRUTE = 1 };
 
-// Calls fn(j, lane_may_hit) for every candidate; lane_may_hit is false for
-// lanes the candidate cannot touch (list mask).  `a_min`/`b_max` bound the
-// live lanes' segments for the list's uniform pre-check.
+// Calls fn(j) for every candidate.  `a_min`/`b_max` bound the live lanes'
+// segments for the list's uniform depth pre-check.
 template <class Fn>
 __device__ __forceinline__ void for_each_candidate(int kind, const WaveMem &M, int count,
                                                    int lane, float a_min, float b_max,
                                                    int n_active, Fn &&fn) {
   if (kind == SRC_LIST) {
     // 64 entries at a time: lane i holds entry base + i; the depth pre-check
-    // is one ballot, and the surviving entries are read back with readlane
+    // is one ballot, and the surviving indices are read back with readlane
     for (int base = 0; base < count; base += 64) {
       const int e = base + lane;
       int id = 0;
-      uint32_t mlo = 0, mhi = 0;
       bool keep = false;
       if (e < count) {
         const int o = (int)(uint32_t)M.u.order[e];
         keep = !(M.l_tin[o] > b_max) && !(M.l_tout[o] < a_min);
         id = M.l_id[o];
-        mlo = M.l_mlo[o];
-        mhi = M.l_mhi[o];
       }
-      for (uint64_t bits = ballot(keep); bits; bits &= bits - 1) {
-        const int src = __builtin_ctzll(bits);
-        const uint64_t mk = join64((uint32_t)__builtin_amdgcn_readlane((int)mlo, src),
-                                   (uint32_t)__builtin_amdgcn_readlane((int)mhi, src));
-        fn(__builtin_amdgcn_readlane(id, src), ((mk >> lane) & 1) != 0);
-      }
+      for (uint64_t bits = ballot(keep); bits; bits &= bits - 1)
+        fn(__builtin_amdgcn_readlane(id, __builtin_ctzll(bits)));
     }
   } else {
-    for (int e = 0; e < n_active; e++) fn(e, true);
+    for (int e = 0; e < n_active; e++) fn(e);
   }
 }
 
@@ -1026,14 +1001,20 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
     win.z1 = n_active;
     win.chunked = false;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    int32_t cnt[kNStatUsed] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t cnt[kNStatUsed];
+#pragma unroll
+    for (int k = 0; k < kNStatUsed; k++) cnt[k] = 0;
+    // statistics builds also time the phases of the tile (shader clock)
+    int64_t cyc_collect = 0, cyc_closest = 0, cyc_t0 = 0, cyc_tile = stats ? clock64() : 0;
     float prev_a = -kInf, prev_b = -kInf;
     int n_dump = 0;
 
     for (;;) {
+      if (stats) cyc_t0 = clock64();
       if (op.ess)
         closest_pass(s, op, n_active, r, tn, tf, dS, ss, ls.error_flag,
                      stats ? &cnt[ST_CLOSEST] : nullptr);
+      if (stats) cyc_closest += clock64() - cyc_t0;
       if (ss.alive) {
         const float a0 = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
         if (!(a0 < tf) || !(T > op.t_eps)) ss.alive = false;
@@ -1049,8 +1030,10 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       }
       if (!ss.alive) { sp.o = 0.0f; sp.dt = 0.0f; sp.i0 = 0; }
       bool go;
+      if (stats) cyc_t0 = clock64();
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
                     cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS], go);
+      if (stats) cyc_collect += clock64() - cyc_t0;
       if (stats && go && win.chunked) cnt[ST_CHUNKED]++;
       const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
       const float lo = go ? a : kInf, hi = go ? b : -kInf;
@@ -1059,13 +1042,15 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
       int nhit = 0;
 
-      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j, bool may) {
-        const bool want = go && may;
+      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j) {
+        const bool want = go;
         if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
+        if (stats) cnt[ST_CAND]++;
         if (ballot(hit) == 0) return;
+        if (stats) cnt[ST_CAND_HIT]++;
         if (hit) {
           nhit++;
           if (stats && !(c.tin <= prev_b && c.tout >= prev_a)) cnt[ST_Q]++;
@@ -1088,8 +1073,13 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
             W2[k] = fmaf(wk[k], cb, W2[k]);
           }
         }
-      }); while (next_chunk(s, M, r, lane, n_active, go, a, b, win.z1, win, stats, ls.error_flag,
-                            cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS]));
+      }); while ([&] {
+        if (stats) cyc_t0 = clock64();
+        const bool more = next_chunk(s, M, r, lane, n_active, go, a, b, win.z1, win, stats,
+                                     ls.error_flag, cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS]);
+        if (stats) cyc_collect += clock64() - cyc_t0;
+        return more;
+      }());
 
       // an empty segment restarts at the next closest hit: inside the window
       // from the list, otherwise through a closest-hit traversal
@@ -1097,8 +1087,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       float best = kInf;
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, [&](int j, bool may) {
-          const bool want = empty && may;
+        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, [&](int j) {
+          const bool want = empty;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
           const Chord c = chord(g, r);
@@ -1129,7 +1119,12 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       }
     }
 
-    if (stats) cnt[ST_BOX_ONLY] += M.cnt_box[lane];
+    if (stats) {
+      cnt[ST_BOX_ONLY] += M.cnt_box[lane];
+      cnt[ST_KCYC_COLLECT] = (int32_t)(cyc_collect >> 10);
+      cnt[ST_KCYC_CLOSEST] = (int32_t)(cyc_closest >> 10);
+      cnt[ST_KCYC_TILE] = (int32_t)((clock64() - cyc_tile) >> 10);
+    }
     if (DUMP) {
       if (px.valid) out.dump_count[dump_slot] = n_dump;
     } else if (px.valid) {
@@ -1239,8 +1234,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       int nhit = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
-      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j, bool may) {
-        const bool want = go && may;
+      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j) {
+        const bool want = go;
         if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
@@ -1298,8 +1293,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         if (win.chunked)
           next_chunk(s, M, r, lane, n_active, any, a, b, 0, win, false, ls.error_flag, dummy_nodes,
                      dummy_leaves, dummy_windows);
-        do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j, bool may) {
-          const bool want = any && may;
+        do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j) {
+          const bool want = any;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
           float opx, opy, opz, dpx, dpy, dpz;
@@ -1365,8 +1360,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       float best = kInf;
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, [&](int j, bool may) {
-          const bool want = empty && may;
+        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, [&](int j) {
+          const bool want = empty;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
           const Chord c = chord(g, r);

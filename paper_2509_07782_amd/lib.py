@@ -14,9 +14,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RGX_LIBRARY", os.path.join(HERE, "librgx.so"))
 
 RGX_OK = 0
-NSTAT = 10
+NSTAT = 15
 STAT_NAMES = ("Q", "P", "samples", "segments", "closest", "box_only", "nodes", "leaves",
-              "windows", "chunked")
+              "windows", "chunked", "cand", "cand_hit", "kcyc_collect", "kcyc_closest",
+              "kcyc_tile")
 
 
 class RgxError(RuntimeError):
