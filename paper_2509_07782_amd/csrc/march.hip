@@ -649,12 +649,48 @@ __device__ __forceinline__ bool cone_box(const Cone &k, const Ray &o, float lx, 
                      &dhi);
 }
 
+// Depth bounds [lo, hi] of every ray of the packet inside one ellipsoid
+// (centre v relative to the apex, size k, scales s, unit quaternion q): a
+// point o + t d of the ellipsoid satisfies |t - v.d| <= k |S R^T d| (its
+// support along d), v.d ranges over [|v| cos(phi + theta), |v| cos(phi - theta)]
+// for the angle phi between v and the axis, and |S R^T d| <= |S R^T u| +
+// max(s) |d - u| with |d - u| <= sin(theta) sqrt(2 / (1 + cos(theta))).
+__device__ __forceinline__ void support_bounds(const Cone &k, float vx, float vy, float vz,
+                                               float kk, float sx, float sy, float sz, float qw,
+                                               float qx, float qy, float qz, float *lo,
+                                               float *hi) {
+  // w = R^T u, R the rotation of the unit quaternion
+  const float R00 = 1.0f - 2.0f * (qy * qy + qz * qz), R01 = 2.0f * (qx * qy - qw * qz),
+              R02 = 2.0f * (qx * qz + qw * qy);
+  const float R10 = 2.0f * (qx * qy + qw * qz), R11 = 1.0f - 2.0f * (qx * qx + qz * qz),
+              R12 = 2.0f * (qy * qz - qw * qx);
+  const float R20 = 2.0f * (qx * qz - qw * qy), R21 = 2.0f * (qy * qz + qw * qx),
+              R22 = 1.0f - 2.0f * (qx * qx + qy * qy);
+  const float w0 = sx * fmaf(R00, k.ux, fmaf(R10, k.uy, R20 * k.uz));
+  const float w1 = sy * fmaf(R01, k.ux, fmaf(R11, k.uy, R21 * k.uz));
+  const float w2 = sz * fmaf(R02, k.ux, fmaf(R12, k.uy, R22 * k.uz));
+  const float du = k.sn * sqrtf(2.0f / (1.0f + k.cs));
+  const float ext = kk * fmaf(fmaxf(sx, fmaxf(sy, sz)), du, sqrtf(fmaf(w0, w0, fmaf(w1, w1, w2 * w2))));
+  const float d = sqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+  const float al = fmaf(vx, k.ux, fmaf(vy, k.uy, vz * k.uz));
+  const float cx = vy * k.uz - vz * k.uy, cy = vz * k.ux - vx * k.uz, cz = vx * k.uy - vy * k.ux;
+  const float perp = sqrtf(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
+  // phi >= theta <=> perp cos(theta) >= al sin(theta); phi <= 90 deg <=> al >= 0
+  const float c_hi = perp * k.cs >= al * k.sn ? fmaf(al, k.cs, perp * k.sn) : d;
+  const float c_lo = al >= 0.0f ? fmaf(al, k.cs, -perp * k.sn) : -d;
+  // margins: FP32 chord ends near tangency, rotation and norm rounding
+  const float pad = fmaf(ext, 1e-3f, fmaf(d, 1e-5f, 1e-6f));
+  *lo = c_lo - ext - pad;
+  *hi = c_hi + ext + pad;
+}
+
 // Collects the list for the rays in `rays` (windows in M.rlo / M.rhi) and
 // the Z range [z0, z1); z1 may be lowered.  Returns the number of list
 // entries, or -1 on a malformed tree (error flag set).
 __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, int lane,
                               uint64_t rays, int n_active, int z0, int &z1, bool stats,
-                              int32_t *err, int32_t &nodes_out, int32_t &leaves_out) {
+                              int32_t *err, int32_t &nodes_out, int32_t &leaves_out,
+                              int64_t *cyc_excl) {
   if (n_active <= 0 || rays == 0 || z0 >= z1) return 0;
   const int n_inner = n_active > 1 ? n_active - 1 : 1;
   int head = 0, tail = 1, staged = 0, count = 0, visits = 0;
@@ -762,10 +798,21 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       if (test) {
         const vf4 *gp = reinterpret_cast<const vf4 *>(s.geom) + 4 * j;
         const vf4 g0 = gp[0], g3 = gp[3];
-        keep = cone_sphere(cone, g0.x - self.ox, g0.y - self.oy, g0.z - self.oz, g3.w, &tmin,
-                           &tmax);
+        const float vx = g0.x - self.ox, vy = g0.y - self.oy, vz = g0.z - self.oz;
+        keep = cone_sphere(cone, vx, vy, vz, g3.w, &tmin, &tmax);
+        if (keep && cone.narrow) {
+          const vf4 *ap = reinterpret_cast<const vf4 *>(s.aux) + 2 * j;
+          const vf4 x0 = ap[0], x1 = ap[1];
+          float lo, hi;
+          support_bounds(cone, vx, vy, vz, sqrtf(g0.w), x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z,
+                         &lo, &hi);
+          tmin = fmaxf(tmin, lo);
+          tmax = fminf(tmax, hi);
+          keep = tmin <= cone.t_hi && tmax >= cone.t_lo;
+        }
       }
       if (stats && ballot(test)) {
+        const int64_t c0 = clock64();
         // statistics only: AABB-only leaves per ray (box met, ellipsoid missed)
         const Gauss g = load_gauss_lane(s.geom, test ? j : 0);
         const float *bx = s.aabb + 6 * (size_t)(test ? j : 0);
@@ -777,6 +824,7 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
           const Chord ch = chord(g, q);
           if (!(ch.exists && ch.tin <= hi && ch.tout >= lo)) atomicAdd(&M.cnt_box[r], 1);
         }
+        if (cyc_excl) *cyc_excl += clock64() - c0;
       }
       leaves_out += k;
       int tot = __popcll(ballot(keep));
@@ -875,7 +923,8 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
                                               const Ray &r, int lane, int n_active, bool alive,
                                               float a, float b, Window &w, bool stats,
                                               int32_t *err, int32_t &nodes, int32_t &leaves,
-                                              int32_t &windows, bool &fits) {
+                                              int32_t &windows, bool &fits,
+                                              int64_t *cyc_excl = nullptr) {
   if (op.brute_force) {
     w.kind = SRC_BRUTE;
     w.chunked = false;
@@ -894,7 +943,7 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
   __builtin_amdgcn_wave_barrier();
   windows++;
   int z1 = n_active;
-  const int cnt = collect_window(s, M, r, lane, rays, n_active, 0, z1, stats, err, nodes, leaves);
+  const int cnt = collect_window(s, M, r, lane, rays, n_active, 0, z1, stats, err, nodes, leaves, cyc_excl);
   w.kind = SRC_LIST;
   w.count = cnt > 0 ? cnt : 0;
   w.z1 = cnt >= 0 ? z1 : n_active;     // a malformed tree ends the rays (error flag set)
@@ -916,7 +965,8 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
 __device__ __forceinline__ bool next_chunk(const SceneDev &s, WaveMem &M, const Ray &r, int lane,
                                            int n_active, bool lanes, float a, float b, int z0,
                                            Window &w, bool stats, int32_t *err, int32_t &nodes,
-                                           int32_t &leaves, int32_t &windows) {
+                                           int32_t &leaves, int32_t &windows,
+                                           int64_t *cyc_excl = nullptr) {
   if (!w.chunked || z0 >= n_active) return false;
   const uint64_t rays = ballot(lanes);
   if (rays == 0) return false;
@@ -925,7 +975,7 @@ __device__ __forceinline__ bool next_chunk(const SceneDev &s, WaveMem &M, const 
   __builtin_amdgcn_wave_barrier();
   windows++;
   int z1 = n_active;
-  const int cnt = collect_window(s, M, r, lane, rays, n_active, z0, z1, stats, err, nodes, leaves);
+  const int cnt = collect_window(s, M, r, lane, rays, n_active, z0, z1, stats, err, nodes, leaves, cyc_excl);
   if (cnt < 0) {
     w.count = 0;
     w.z1 = n_active;
@@ -1006,6 +1056,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
     for (int k = 0; k < kNStatUsed; k++) cnt[k] = 0;
     // statistics builds also time the phases of the tile (shader clock)
     int64_t cyc_collect = 0, cyc_closest = 0, cyc_t0 = 0, cyc_tile = stats ? clock64() : 0;
+    int64_t cyc_boxstat = 0;   // statistics-only work inside the collection
     float prev_a = -kInf, prev_b = -kInf;
     int n_dump = 0;
 
@@ -1032,7 +1083,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       bool go;
       if (stats) cyc_t0 = clock64();
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
-                    cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS], go);
+                    cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS], go,
+                    stats ? &cyc_boxstat : nullptr);
       if (stats) cyc_collect += clock64() - cyc_t0;
       if (stats && go && win.chunked) cnt[ST_CHUNKED]++;
       const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
@@ -1076,7 +1128,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       }); while ([&] {
         if (stats) cyc_t0 = clock64();
         const bool more = next_chunk(s, M, r, lane, n_active, go, a, b, win.z1, win, stats,
-                                     ls.error_flag, cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS]);
+                                     ls.error_flag, cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS],
+                                     stats ? &cyc_boxstat : nullptr);
         if (stats) cyc_collect += clock64() - cyc_t0;
         return more;
       }());
@@ -1121,9 +1174,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
 
     if (stats) {
       cnt[ST_BOX_ONLY] += M.cnt_box[lane];
-      cnt[ST_KCYC_COLLECT] = (int32_t)(cyc_collect >> 10);
+      cnt[ST_KCYC_COLLECT] = (int32_t)((cyc_collect - cyc_boxstat) >> 10);
       cnt[ST_KCYC_CLOSEST] = (int32_t)(cyc_closest >> 10);
-      cnt[ST_KCYC_TILE] = (int32_t)((clock64() - cyc_tile) >> 10);
+      cnt[ST_KCYC_TILE] = (int32_t)((clock64() - cyc_tile - cyc_boxstat) >> 10);
     }
     if (DUMP) {
       if (px.valid) out.dump_count[dump_slot] = n_dump;
