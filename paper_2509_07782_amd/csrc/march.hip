@@ -880,22 +880,38 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
 enum SourceKind { SRC_LIST = 0, SRC_BRUTE = 1 };
 
 // Calls fn(j) for every candidate.  `a_min`/`b_max` bound the live lanes'
-// segments for the list's uniform depth pre-check.
+// segments for the list's uniform depth pre-check; when `lanes` is non-zero,
+// an entry must also overlap the segment [a, b] of one of those lanes.
 template <class Fn>
 __device__ __forceinline__ void for_each_candidate(int kind, const WaveMem &M, int count,
                                                    int lane, float a_min, float b_max,
-                                                   int n_active, Fn &&fn) {
+                                                   int n_active, uint64_t lanes, float a,
+                                                   float b, Fn &&fn) {
   if (kind == SRC_LIST) {
     // 64 entries at a time: lane i holds entry base + i; the depth pre-check
-    // is one ballot, and the surviving indices are read back with readlane
+    // is one ballot (then a pass over the marching lanes' segments), and the
+    // surviving indices are read back with readlane
     for (int base = 0; base < count; base += 64) {
       const int e = base + lane;
       int id = 0;
       bool keep = false;
+      float tin = 0.0f, tout = 0.0f;
       if (e < count) {
         const int o = (int)(uint32_t)M.u.order[e];
-        keep = !(M.l_tin[o] > b_max) && !(M.l_tout[o] < a_min);
+        tin = M.l_tin[o];
+        tout = M.l_tout[o];
+        keep = !(tin > b_max) && !(tout < a_min);
         id = M.l_id[o];
+      }
+      if (lanes && ballot(keep)) {
+        bool any = false;
+        for (uint64_t L = lanes; L; L &= L - 1) {
+          const int l = __builtin_ctzll(L);
+          const float al = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a), l));
+          const float bl = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, b), l));
+          any = any || (!(tin > bl) && !(tout < al));
+        }
+        keep = keep && any;
       }
       for (uint64_t bits = ballot(keep); bits; bits &= bits - 1)
         fn(__builtin_amdgcn_readlane(id, __builtin_ctzll(bits)));
@@ -1094,7 +1110,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
       int nhit = 0;
 
-      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j) {
+      const uint64_t go_lanes = ballot(go);
+      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, go_lanes, a, b,
+                            [&](int j) {
         const bool want = go;
         if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
@@ -1140,7 +1158,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       float best = kInf;
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, [&](int j) {
+        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, 0ull, 0.0f, 0.0f,
+                           [&](int j) {
           const bool want = empty;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
@@ -1287,7 +1306,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       int nhit = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
-      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j) {
+      const uint64_t go_lanes = ballot(go);
+      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, go_lanes, a, b,
+                            [&](int j) {
         const bool want = go;
         if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
@@ -1346,7 +1367,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         if (win.chunked)
           next_chunk(s, M, r, lane, n_active, any, a, b, 0, win, false, ls.error_flag, dummy_nodes,
                      dummy_leaves, dummy_windows);
-        do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, [&](int j) {
+        const uint64_t any_lanes = ballot(any);
+        do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, any_lanes, a, b,
+                              [&](int j) {
           const bool want = any;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
@@ -1413,7 +1436,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       float best = kInf;
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, [&](int j) {
+        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, 0ull, 0.0f, 0.0f,
+                           [&](int j) {
           const bool want = empty;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
