@@ -431,8 +431,11 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
 // the farthest window end, applied to bounding spheres (of a node's child
 // boxes, of a leaf's ellipsoid).  Exact per-ray chords are left to the
 // segment loop, which computes them anyway.  The traversal is node-parallel:
-// a FIFO frontier of (node, first leaf) lives in LDS and each round hands up
-// to 64 frontier nodes to the 64 lanes, which load them independently.  When
+// the frontier of (node, first leaf) is an LDS stack ordered by first leaf,
+// smallest on top; each round hands the (up to) 64 lowest subtrees to the 64
+// lanes, which load them independently, and their children go back on top in
+// order -- a 64-wide depth-first walk in Z order, whose frontier stays narrow.
+// When
 // the frontier or the list would overflow, z1 is lowered (a radix select over
 // the pending Z indices) and everything at or beyond it is dropped, so the
 // result is always complete for [z0, z1); the caller continues from z1 with
@@ -440,9 +443,9 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
 // its Gaussians in Z order whatever window, chunking or packet produced the
 // list -- the order of brute force.
 
-constexpr int kRingCap = 512;    // frontier entries (power of two)
+constexpr int kRingCap = 256;    // frontier (stack) entries
 constexpr int kStageCap = 160;   // staged leaves; a round adds at most 2 per node
-constexpr int kListCap = 512;    // window list entries (power of two; bitonic sort)
+constexpr int kListCap = 384;    // window list entries (multiple of 64)
 
 struct WaveMem {
   float rdx[64], rdy[64], rdz[64], rix[64], riy[64], riz[64], rlo[64], rhi[64];
@@ -451,12 +454,17 @@ struct WaveMem {
       int32_t ring_id[kRingCap], ring_first[kRingCap];
       int32_t st_id[kStageCap];
     } c;
-    uint64_t order[kListCap];      // afterwards: (Gaussian index << 32 | list slot), sorted
+    int32_t order[kListCap];       // afterwards: list slots in Z-index order
   } u;
   int32_t l_id[kListCap];
+  uint32_t l_mlo[kListCap], l_mhi[kListCap];   // rays whose bounding-sphere chord meets their window
   float l_tin[kListCap], l_tout[kListCap];
   int32_t cnt_box[64];             // per-ray AABB-only leaf count (statistics)
 };
+
+__device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) {
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -507,10 +515,13 @@ __device__ __forceinline__ int compact_list(WaveMem &M, int lane, int count, int
   for (int e0 = 0; e0 < count; e0 += 64) {
     const int e = e0 + lane;
     int id = 0;
+    uint32_t mlo = 0, mhi = 0;
     float tin = 0.0f, tout = 0.0f;
     bool keep = false;
     if (e < count) {
       id = M.l_id[e];
+      mlo = M.l_mlo[e];
+      mhi = M.l_mhi[e];
       tin = M.l_tin[e];
       tout = M.l_tout[e];
       keep = id < z1;
@@ -520,6 +531,8 @@ __device__ __forceinline__ int compact_list(WaveMem &M, int lane, int count, int
     if (keep) {
       const int pos = base + __popcll(b & below);
       M.l_id[pos] = id;
+      M.l_mlo[pos] = mlo;
+      M.l_mhi[pos] = mhi;
       M.l_tin[pos] = tin;
       M.l_tout[pos] = tout;
     }
@@ -529,14 +542,14 @@ __device__ __forceinline__ int compact_list(WaveMem &M, int lane, int count, int
   return base;
 }
 
-// Keeps the pending frontier entries whose first leaf is below z1 (order
-// preserved, same scheme); returns the new tail.
+// Keeps the frontier entries in [head, tail) whose first leaf is below z1
+// (order preserved, same scheme); returns the new end.
 __device__ __forceinline__ int compact_ring(WaveMem &M, int lane, int head, int tail, int z1) {
   const uint64_t below = lanes_below(lane);
   int base = head;
   for (int e0 = head; e0 < tail; e0 += 64) {
     const int e = e0 + lane;
-    const int slot = e & (kRingCap - 1);
+    const int slot = e;
     int id = 0, first = 0;
     bool keep = false;
     if (e < tail) {
@@ -547,7 +560,7 @@ __device__ __forceinline__ int compact_ring(WaveMem &M, int lane, int head, int 
     __builtin_amdgcn_wave_barrier();
     const uint64_t b = ballot(keep);
     if (keep) {
-      const int d = (base + __popcll(b & below)) & (kRingCap - 1);
+      const int d = base + __popcll(b & below);
       M.u.c.ring_id[d] = id;
       M.u.c.ring_first[d] = first;
     }
@@ -557,39 +570,29 @@ __device__ __forceinline__ int compact_ring(WaveMem &M, int lane, int head, int 
   return base;
 }
 
-// Bitonic sort (by Gaussian index) of the window list's order keys in LDS;
-// entries with index >= z1 sort last and are dropped.  Returns the count.
+// Orders the list by Gaussian (Z) index: entries with index >= z1 are
+// dropped first, then each entry's rank (the number of smaller indices; the
+// indices are distinct) places its slot in M.u.order.  Returns the count.
 __device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int z1) {
-  int p2 = 1;
-  while (p2 < count) p2 <<= 1;
-  int valid = 0;
-  for (int e0 = 0; e0 < p2; e0 += 64) {
-    const int e = e0 + lane;
-    bool ok = false;
-    if (e < p2) {
-      const int id = e < count ? M.l_id[e] : 0;
-      ok = e < count && id < z1;
-      M.u.order[e] = ok ? ((uint64_t)(uint32_t)id << 32) | (uint32_t)e : ~0ull;
-    }
-    valid += __popcll(ballot(ok));
+  count = compact_list(M, lane, count, z1);
+  int id[kListCap / 64], rank[kListCap / 64];
+#pragma unroll
+  for (int q = 0; q < kListCap / 64; q++) {
+    id[q] = lane + 64 * q < count ? M.l_id[lane + 64 * q] : 0x7fffffff;
+    rank[q] = 0;
   }
-  for (int k = 2; k <= p2; k <<= 1) {
-    for (int j = k >> 1; j >= 1; j >>= 1) {
-      __builtin_amdgcn_wave_barrier();
-      for (int e = lane; e < p2; e += 64) {
-        const int f = e ^ j;
-        if (f > e) {
-          const uint64_t x = M.u.order[e], y = M.u.order[f];
-          const bool up = (e & k) == 0;
-          if ((x > y) == up) { M.u.order[e] = y; M.u.order[f] = x; }
-        }
-      }
-    }
+  for (int f = 0; f < count; f++) {
+    const int x = M.l_id[f];                 // same address in every lane: broadcast
+#pragma unroll
+    for (int q = 0; q < kListCap / 64; q++) rank[q] += x < id[q] ? 1 : 0;
   }
   __builtin_amdgcn_wave_barrier();
-  return valid;
+#pragma unroll
+  for (int q = 0; q < kListCap / 64; q++)
+    if (lane + 64 * q < count) M.u.order[rank[q]] = lane + 64 * q;
+  __builtin_amdgcn_wave_barrier();
+  return count;
 }
-
 
 // The packet bound: apex o, unit axis u, half-angle (cos, sin) padded
 // outward, and the depth shell [t_lo, t_hi] (distances from o).
@@ -693,7 +696,8 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
                               int64_t *cyc_excl) {
   if (n_active <= 0 || rays == 0 || z0 >= z1) return 0;
   const int n_inner = n_active > 1 ? n_active - 1 : 1;
-  int head = 0, tail = 1, staged = 0, count = 0, visits = 0;
+  // stack S[0, sp): first leaf strictly decreasing towards the top S[sp-1]
+  int sp = 1, staged = 0, count = 0, visits = 0;
   if (lane == 0) {
     M.u.c.ring_id[0] = 0;
     M.u.c.ring_first[0] = 0;
@@ -702,16 +706,16 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
   const uint64_t below = lanes_below(lane);
   for (;;) {
     __builtin_amdgcn_wave_barrier();
-    const int n = min(min(64, tail - head), (kStageCap - staged) >> 1);
+    const int n = min(min(64, sp), (kStageCap - staged) >> 1);
     if (n > 0) {
       int id = 0;
       bool live = false;
-      if (lane < n) {
-        const int slot = (head + lane) & (kRingCap - 1);
+      if (lane < n) {                            // lane 0 takes the top (lowest Z)
+        const int slot = sp - 1 - lane;
         id = M.u.c.ring_id[slot];
         live = M.u.c.ring_first[slot] < z1;      // else cut off by a later z1
       }
-      head += n;
+      sp -= n;
       visits += __popcll(ballot(live));
       if (visits > n_inner) { if (err) *err = 2; return -1; }
       vf4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0}, c = {0, 0, 0, 0}, d = {0, 0, 0, 0};
@@ -737,39 +741,40 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       const bool lL = hL && cl < 0, rL = hR && cr < 0;
       {
         int tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
-        if (tail + tot - head > kRingCap) {
+        if (sp + tot > kRingCap) {
           // frontier overflow: lower z1 to keep half the pending subtrees
           int v[kRingCap / 64 + 2];
           bool ok[kRingCap / 64 + 2];
-          const int pend = tail - head;
 #pragma unroll
           for (int k = 0; k < kRingCap / 64; k++) {
             const int e = lane + 64 * k;
-            ok[k] = e < pend;
-            v[k] = ok[k] ? M.u.c.ring_first[(head + e) & (kRingCap - 1)] : 0;
+            ok[k] = e < sp;
+            v[k] = ok[k] ? M.u.c.ring_first[e] : 0;
           }
           v[kRingCap / 64] = nlo; ok[kRingCap / 64] = lI;
           v[kRingCap / 64 + 1] = gamma + 1; ok[kRingCap / 64 + 1] = rI;
           z1 = select_cut(v, ok, z0 + 1, z1, kRingCap / 2);
-          tail = compact_ring(M, lane, head, tail, z1);
+          sp = compact_ring(M, lane, 0, sp, z1);
           lI = lI && nlo < z1;
           rI = rI && gamma + 1 < z1;
           tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
         }
+        // the children are below every entry left on the stack; in lane
+        // order, left before right, they are ascending, so the k-th of them
+        // goes to S[sp + tot - 1 - k]
         const uint64_t b1 = ballot(lI || rI), b2 = ballot(lI && rI);
-        int pos = tail + __popcll(b1 & below) + __popcll(b2 & below);
+        const int rank = __popcll(b1 & below) + __popcll(b2 & below);
+        int pos = sp + tot - 1 - rank;
         if (lI) {
-          const int slot = pos & (kRingCap - 1);
-          M.u.c.ring_id[slot] = cl;
-          M.u.c.ring_first[slot] = nlo;
-          pos++;
+          M.u.c.ring_id[pos] = cl;
+          M.u.c.ring_first[pos] = nlo;
+          pos--;
         }
         if (rI) {
-          const int slot = pos & (kRingCap - 1);
-          M.u.c.ring_id[slot] = cr;
-          M.u.c.ring_first[slot] = gamma + 1;
+          M.u.c.ring_id[pos] = cr;
+          M.u.c.ring_first[pos] = gamma + 1;
         }
-        tail += tot;
+        sp += tot;
       }
       {
         // leaves past a lowered z1 are filtered when tested
@@ -781,7 +786,7 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         staged += tot;
       }
     }
-    const bool done = head == tail;
+    const bool done = sp == 0;
     // tests of staged leaves, 64 at a time, in staging order: the bounding
     // sphere of the ellipsoid against the packet gives the entry's depth bounds
     while (staged >= 64 || (done && staged > 0)) {
@@ -794,12 +799,13 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         test = j < z1;
       }
       bool keep = false;
-      float tmin = 0.0f, tmax = 0.0f;
+      float tmin = 0.0f, tmax = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f, rad = 0.0f;
       if (test) {
         const vf4 *gp = reinterpret_cast<const vf4 *>(s.geom) + 4 * j;
         const vf4 g0 = gp[0], g3 = gp[3];
-        const float vx = g0.x - self.ox, vy = g0.y - self.oy, vz = g0.z - self.oz;
-        keep = cone_sphere(cone, vx, vy, vz, g3.w, &tmin, &tmax);
+        vx = g0.x - self.ox; vy = g0.y - self.oy; vz = g0.z - self.oz;
+        rad = g3.w;
+        keep = cone_sphere(cone, vx, vy, vz, rad, &tmin, &tmax);
         if (keep && cone.narrow) {
           const vf4 *ap = reinterpret_cast<const vf4 *>(s.aux) + 2 * j;
           const vf4 x0 = ap[0], x1 = ap[1];
@@ -810,6 +816,33 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
           tmax = fminf(tmax, hi);
           keep = tmin <= cone.t_hi && tmax >= cone.t_lo;
         }
+      }
+      // per ray: the chord of the bounding sphere (within the packet bounds)
+      // against the ray's window gives the entry's ray mask and depth bounds
+      uint64_t hitm = 0;
+      if (ballot(keep)) {
+        const float d2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
+        const float rp = fmaf(sqrtf(d2), 1e-5f, rad * 1.001f);
+        const float rp2 = rp * rp;
+        float lo_k = kInf, hi_k = -kInf;
+        for (uint64_t rem = rays; rem; rem &= rem - 1) {
+          const int r = __builtin_ctzll(rem);
+          const float dx = M.rdx[r], dy = M.rdy[r], dz = M.rdz[r];
+          const float wlo = M.rlo[r], whi = M.rhi[r];
+          const float tc = fmaf(vx, dx, fmaf(vy, dy, vz * dz));
+          const float cx = vy * dz - vz * dy, cy = vz * dx - vx * dz, cz = vx * dy - vy * dx;
+          const float h2 = rp2 - fmaf(cx, cx, fmaf(cy, cy, cz * cz));
+          const float h = sqrtf(fmaxf(h2, 0.0f));
+          const float t0 = fmaxf(tc - h, tmin), t1 = fminf(tc + h, tmax);
+          if (keep && h2 >= 0.0f && t0 <= whi && t1 >= wlo) {
+            hitm |= 1ull << r;
+            lo_k = fminf(lo_k, t0);
+            hi_k = fmaxf(hi_k, t1);
+          }
+        }
+        keep = hitm != 0;
+        tmin = lo_k;
+        tmax = hi_k;
       }
       if (stats && ballot(test)) {
         const int64_t c0 = clock64();
@@ -849,6 +882,8 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       if (keep) {
         const int pos = count + __popcll(bk & below);
         M.l_id[pos] = j;
+        M.l_mlo[pos] = (uint32_t)hitm;
+        M.l_mhi[pos] = (uint32_t)(hitm >> 32);
         M.l_tin[pos] = tmin;
         M.l_tout[pos] = tmax;
       }
@@ -879,9 +914,11 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
 
 enum SourceKind { SRC_LIST = 0, SRC_BRUTE = 1 };
 
-// Calls fn(j) for every candidate.  `a_min`/`b_max` bound the live lanes'
-// segments for the list's uniform depth pre-check; when `lanes` is non-zero,
-// an entry must also overlap the segment [a, b] of one of those lanes.
+// Calls fn(j, lane_may_hit) for every candidate; lane_may_hit is false for
+// lanes the candidate cannot touch (list mask).  `a_min`/`b_max` bound the
+// live lanes' segments for the list's uniform depth pre-check; when `lanes`
+// is non-zero, an entry must also overlap the segment [a, b] of one of those
+// lanes that its mask holds.
 template <class Fn>
 __device__ __forceinline__ void for_each_candidate(int kind, const WaveMem &M, int count,
                                                    int lane, float a_min, float b_max,
@@ -894,13 +931,15 @@ __device__ __forceinline__ void for_each_candidate(int kind, const WaveMem &M, i
     for (int base = 0; base < count; base += 64) {
       const int e = base + lane;
       int id = 0;
+      uint64_t mk = 0;
       bool keep = false;
       float tin = 0.0f, tout = 0.0f;
       if (e < count) {
-        const int o = (int)(uint32_t)M.u.order[e];
+        const int o = M.u.order[e];
         tin = M.l_tin[o];
         tout = M.l_tout[o];
-        keep = !(tin > b_max) && !(tout < a_min);
+        mk = join64(M.l_mlo[o], M.l_mhi[o]);
+        keep = !(tin > b_max) && !(tout < a_min) && (lanes == 0 || (mk & lanes) != 0);
         id = M.l_id[o];
       }
       if (lanes && ballot(keep)) {
@@ -909,15 +948,19 @@ __device__ __forceinline__ void for_each_candidate(int kind, const WaveMem &M, i
           const int l = __builtin_ctzll(L);
           const float al = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a), l));
           const float bl = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, b), l));
-          any = any || (!(tin > bl) && !(tout < al));
+          any = any || (((mk >> l) & 1) && !(tin > bl) && !(tout < al));
         }
         keep = keep && any;
       }
-      for (uint64_t bits = ballot(keep); bits; bits &= bits - 1)
-        fn(__builtin_amdgcn_readlane(id, __builtin_ctzll(bits)));
+      for (uint64_t bits = ballot(keep); bits; bits &= bits - 1) {
+        const int src = __builtin_ctzll(bits);
+        const uint64_t m = join64((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mk, src),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mk >> 32), src));
+        fn(__builtin_amdgcn_readlane(id, src), ((m >> lane) & 1) != 0);
+      }
     }
   } else {
-    for (int e = 0; e < n_active; e++) fn(e);
+    for (int e = 0; e < n_active; e++) fn(e, true);
   }
 }
 
@@ -1112,8 +1155,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
 
       const uint64_t go_lanes = ballot(go);
       do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, go_lanes, a, b,
-                            [&](int j) {
-        const bool want = go;
+                            [&](int j, bool may) {
+        const bool want = go && may;
         if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
@@ -1159,8 +1202,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
         for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, 0ull, 0.0f, 0.0f,
-                           [&](int j) {
-          const bool want = empty;
+                           [&](int j, bool may) {
+          const bool want = empty && may;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
           const Chord c = chord(g, r);
@@ -1308,8 +1351,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       // pass A: the forward's per-sample sums, in the forward's order
       const uint64_t go_lanes = ballot(go);
       do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, go_lanes, a, b,
-                            [&](int j) {
-        const bool want = go;
+                            [&](int j, bool may) {
+        const bool want = go && may;
         if (ballot(want) == 0) return;
         const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
@@ -1369,8 +1412,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
                      dummy_leaves, dummy_windows);
         const uint64_t any_lanes = ballot(any);
         do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, any_lanes, a, b,
-                              [&](int j) {
-          const bool want = any;
+                              [&](int j, bool may) {
+          const bool want = any && may;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
           float opx, opy, opz, dpx, dpy, dpz;
@@ -1437,8 +1480,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
         for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, 0ull, 0.0f, 0.0f,
-                           [&](int j) {
-          const bool want = empty;
+                           [&](int j, bool may) {
+          const bool want = empty && may;
           if (ballot(want) == 0) return;
           const Gauss g = load_gauss(s.geom, j);
           const Chord c = chord(g, r);
