@@ -457,7 +457,6 @@ struct WaveMem {
     int32_t order[kListCap];       // afterwards: list slots in Z-index order
   } u;
   int32_t l_id[kListCap];
-  uint32_t l_mlo[kListCap], l_mhi[kListCap];   // rays whose bounding-sphere chord meets their window
   float l_tin[kListCap], l_tout[kListCap];
   int32_t cnt_box[64];             // per-ray AABB-only leaf count (statistics)
 };
@@ -515,13 +514,10 @@ __device__ __forceinline__ int compact_list(WaveMem &M, int lane, int count, int
   for (int e0 = 0; e0 < count; e0 += 64) {
     const int e = e0 + lane;
     int id = 0;
-    uint32_t mlo = 0, mhi = 0;
     float tin = 0.0f, tout = 0.0f;
     bool keep = false;
     if (e < count) {
       id = M.l_id[e];
-      mlo = M.l_mlo[e];
-      mhi = M.l_mhi[e];
       tin = M.l_tin[e];
       tout = M.l_tout[e];
       keep = id < z1;
@@ -531,8 +527,6 @@ __device__ __forceinline__ int compact_list(WaveMem &M, int lane, int count, int
     if (keep) {
       const int pos = base + __popcll(b & below);
       M.l_id[pos] = id;
-      M.l_mlo[pos] = mlo;
-      M.l_mhi[pos] = mhi;
       M.l_tin[pos] = tin;
       M.l_tout[pos] = tout;
     }
@@ -799,13 +793,12 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         test = j < z1;
       }
       bool keep = false;
-      float tmin = 0.0f, tmax = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f, rad = 0.0f;
+      float tmin = 0.0f, tmax = 0.0f;
       if (test) {
         const vf4 *gp = reinterpret_cast<const vf4 *>(s.geom) + 4 * j;
         const vf4 g0 = gp[0], g3 = gp[3];
-        vx = g0.x - self.ox; vy = g0.y - self.oy; vz = g0.z - self.oz;
-        rad = g3.w;
-        keep = cone_sphere(cone, vx, vy, vz, rad, &tmin, &tmax);
+        const float vx = g0.x - self.ox, vy = g0.y - self.oy, vz = g0.z - self.oz;
+        keep = cone_sphere(cone, vx, vy, vz, g3.w, &tmin, &tmax);
         if (keep && cone.narrow) {
           const vf4 *ap = reinterpret_cast<const vf4 *>(s.aux) + 2 * j;
           const vf4 x0 = ap[0], x1 = ap[1];
@@ -816,33 +809,6 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
           tmax = fminf(tmax, hi);
           keep = tmin <= cone.t_hi && tmax >= cone.t_lo;
         }
-      }
-      // per ray: the chord of the bounding sphere (within the packet bounds)
-      // against the ray's window gives the entry's ray mask and depth bounds
-      uint64_t hitm = 0;
-      if (ballot(keep)) {
-        const float d2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
-        const float rp = fmaf(sqrtf(d2), 1e-5f, rad * 1.001f);
-        const float rp2 = rp * rp;
-        float lo_k = kInf, hi_k = -kInf;
-        for (uint64_t rem = rays; rem; rem &= rem - 1) {
-          const int r = __builtin_ctzll(rem);
-          const float dx = M.rdx[r], dy = M.rdy[r], dz = M.rdz[r];
-          const float wlo = M.rlo[r], whi = M.rhi[r];
-          const float tc = fmaf(vx, dx, fmaf(vy, dy, vz * dz));
-          const float cx = vy * dz - vz * dy, cy = vz * dx - vx * dz, cz = vx * dy - vy * dx;
-          const float h2 = rp2 - fmaf(cx, cx, fmaf(cy, cy, cz * cz));
-          const float h = sqrtf(fmaxf(h2, 0.0f));
-          const float t0 = fmaxf(tc - h, tmin), t1 = fminf(tc + h, tmax);
-          if (keep && h2 >= 0.0f && t0 <= whi && t1 >= wlo) {
-            hitm |= 1ull << r;
-            lo_k = fminf(lo_k, t0);
-            hi_k = fmaxf(hi_k, t1);
-          }
-        }
-        keep = hitm != 0;
-        tmin = lo_k;
-        tmax = hi_k;
       }
       if (stats && ballot(test)) {
         const int64_t c0 = clock64();
@@ -882,8 +848,6 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       if (keep) {
         const int pos = count + __popcll(bk & below);
         M.l_id[pos] = j;
-        M.l_mlo[pos] = (uint32_t)hitm;
-        M.l_mhi[pos] = (uint32_t)(hitm >> 32);
         M.l_tin[pos] = tmin;
         M.l_tout[pos] = tmax;
       }
@@ -914,53 +878,48 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
 
 enum SourceKind { SRC_LIST = 0, SRC_BRUTE = 1 };
 
-// Calls fn(j, lane_may_hit) for every candidate; lane_may_hit is false for
-// lanes the candidate cannot touch (list mask).  `a_min`/`b_max` bound the
-// live lanes' segments for the list's uniform depth pre-check; when `lanes`
-// is non-zero, an entry must also overlap the segment [a, b] of one of those
-// lanes that its mask holds.
+// Reads lane `src`'s copy of a geometry record (wave-uniform result).
+__device__ __forceinline__ Gauss gauss_from_lane(const Gauss &v, int src) {
+  Gauss g;
+  auto rl = [src](float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), src));
+  };
+  g.mx = rl(v.mx); g.my = rl(v.my); g.mz = rl(v.mz); g.k2 = rl(v.k2);
+#pragma unroll
+  for (int k = 0; k < 9; k++) g.m[k] = rl(v.m[k]);
+  g.sig = rl(v.sig); g.l2sig = rl(v.l2sig);
+  return g;
+}
+
+// Calls fn(j, g) for every candidate j with its geometry record g.
+// `a_min`/`b_max` bound the live lanes' segments for the list's uniform
+// depth pre-check.  List entries are taken 64 at a time: lane i holds entry
+// base + i and loads that entry's geometry, so one memory round trip serves
+// the whole block; the surviving candidates are then read back with readlane.
 template <class Fn>
-__device__ __forceinline__ void for_each_candidate(int kind, const WaveMem &M, int count,
-                                                   int lane, float a_min, float b_max,
-                                                   int n_active, uint64_t lanes, float a,
-                                                   float b, Fn &&fn) {
+__device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, const WaveMem &M,
+                                                   int count, int lane, float a_min, float b_max,
+                                                   int n_active, Fn &&fn) {
   if (kind == SRC_LIST) {
-    // 64 entries at a time: lane i holds entry base + i; the depth pre-check
-    // is one ballot (then a pass over the marching lanes' segments), and the
-    // surviving indices are read back with readlane
     for (int base = 0; base < count; base += 64) {
       const int e = base + lane;
       int id = 0;
-      uint64_t mk = 0;
       bool keep = false;
-      float tin = 0.0f, tout = 0.0f;
       if (e < count) {
         const int o = M.u.order[e];
-        tin = M.l_tin[o];
-        tout = M.l_tout[o];
-        mk = join64(M.l_mlo[o], M.l_mhi[o]);
-        keep = !(tin > b_max) && !(tout < a_min) && (lanes == 0 || (mk & lanes) != 0);
+        keep = !(M.l_tin[o] > b_max) && !(M.l_tout[o] < a_min);
         id = M.l_id[o];
       }
-      if (lanes && ballot(keep)) {
-        bool any = false;
-        for (uint64_t L = lanes; L; L &= L - 1) {
-          const int l = __builtin_ctzll(L);
-          const float al = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a), l));
-          const float bl = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, b), l));
-          any = any || (((mk >> l) & 1) && !(tin > bl) && !(tout < al));
-        }
-        keep = keep && any;
-      }
-      for (uint64_t bits = ballot(keep); bits; bits &= bits - 1) {
+      const uint64_t bits0 = ballot(keep);
+      if (!bits0) continue;
+      const Gauss mine = load_gauss_lane(s.geom, keep ? id : 0);
+      for (uint64_t bits = bits0; bits; bits &= bits - 1) {
         const int src = __builtin_ctzll(bits);
-        const uint64_t m = join64((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mk, src),
-                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mk >> 32), src));
-        fn(__builtin_amdgcn_readlane(id, src), ((m >> lane) & 1) != 0);
+        fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src));
       }
     }
   } else {
-    for (int e = 0; e < n_active; e++) fn(e, true);
+    for (int e = 0; e < n_active; e++) fn(e, load_gauss(s.geom, e));
   }
 }
 
@@ -1153,12 +1112,10 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
       int nhit = 0;
 
-      const uint64_t go_lanes = ballot(go);
-      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, go_lanes, a, b,
-                            [&](int j, bool may) {
-        const bool want = go && may;
+      do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
+                            [&](int j, const Gauss &g) {
+        const bool want = go;
         if (ballot(want) == 0) return;
-        const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
         if (stats) cnt[ST_CAND]++;
@@ -1201,12 +1158,11 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       float best = kInf;
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, 0ull, 0.0f, 0.0f,
-                           [&](int j, bool may) {
-          const bool want = empty && may;
+        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active,
+                           [&](int j, const Gauss &g) {
+          const bool want = empty;
           if (ballot(want) == 0) return;
-          const Gauss g = load_gauss(s.geom, j);
-          const Chord c = chord(g, r);
+            const Chord c = chord(g, r);
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
         });
       }
@@ -1349,12 +1305,10 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       int nhit = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
-      const uint64_t go_lanes = ballot(go);
-      do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, go_lanes, a, b,
-                            [&](int j, bool may) {
-        const bool want = go && may;
+      do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
+                            [&](int j, const Gauss &g) {
+        const bool want = go;
         if (ballot(want) == 0) return;
-        const Gauss g = load_gauss(s.geom, j);
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
         if (ballot(hit) == 0) return;
@@ -1410,13 +1364,11 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         if (win.chunked)
           next_chunk(s, M, r, lane, n_active, any, a, b, 0, win, false, ls.error_flag, dummy_nodes,
                      dummy_leaves, dummy_windows);
-        const uint64_t any_lanes = ballot(any);
-        do for_each_candidate(win.kind, M, win.count, lane, a_min, b_max, n_active, any_lanes, a, b,
-                              [&](int j, bool may) {
-          const bool want = any && may;
+        do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
+                              [&](int j, const Gauss &g) {
+          const bool want = any;
           if (ballot(want) == 0) return;
-          const Gauss g = load_gauss(s.geom, j);
-          float opx, opy, opz, dpx, dpy, dpz;
+            float opx, opy, opz, dpx, dpy, dpz;
           ray_local(g, r, opx, opy, opz, dpx, dpy, dpz);
           const Chord c = chord(g, r);
           const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
@@ -1479,12 +1431,11 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       float best = kInf;
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, M, win.count, lane, bmin, kInf, n_active, 0ull, 0.0f, 0.0f,
-                           [&](int j, bool may) {
-          const bool want = empty && may;
+        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active,
+                           [&](int j, const Gauss &g) {
+          const bool want = empty;
           if (ballot(want) == 0) return;
-          const Gauss g = load_gauss(s.geom, j);
-          const Chord c = chord(g, r);
+            const Chord c = chord(g, r);
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
         });
       }
