@@ -121,7 +121,7 @@ enum {
   RGX_STAT_LEAVES,       /* leaves the wave visited for the segment collections */
   RGX_STAT_WINDOWS,      /* window collections the wave made (attempts included) */
   RGX_STAT_CHUNKED,      /* segments whose candidates were collected in several Z chunks */
-  RGX_STAT_CAND,         /* per wave: candidates evaluated (some lane may hit them) */
+  RGX_STAT_CAND,         /* per wave: candidates passing the window list's depth pre-check */
   RGX_STAT_CAND_HIT,     /* per wave: candidates that some lane hit */
   RGX_STAT_KCYC_COLLECT, /* per wave: shader-clock kilocycles in window collection */
   RGX_STAT_KCYC_CLOSEST, /* per wave: kilocycles in closest-hit queries */
@@ -133,14 +133,21 @@ enum {
 rgx_status rgx_create(int device, rgx_context **out);
 void rgx_destroy(rgx_context *ctx);
 
+/* Largest supported number of Gaussians (the marching kernels sort window
+   lists on 32-bit keys that hold a 23-bit Z index). */
+#define RGX_MAX_GAUSSIANS (1 << 23)
+
 /* Build (or rebuild in place when *bvh is non-NULL) the acceleration
    structure: per-Gaussian preprocessing (R from the normalised quaternion,
    s = exp(l), M = S^-1 R^T, k^2 = 2 ln(sigma~/sigma_eps), minimal AABB
-   half-lengths L_i = k sqrt(sum_j r_ij^2 s_j^2) padded outward), Morton keys
-   of the means quantised over their bounds (Sec. 3.3), a stable radix sort,
-   the Z-ordered pack and a Karras LBVH with bottom-up refit.  Allocates device
-   memory when the structure must grow (never during stream capture).  The
-   parameters are copied; the caller may change them afterwards. */
+   half-lengths L_i = k sqrt(sum_j r_ij^2 s_j^2) padded outward, bounding
+   sphere radius k max(s)), Morton keys of the means quantised over their
+   bounds (Sec. 3.3), a stable radix sort, the Z-ordered pack and a Karras
+   LBVH whose node boxes are range unions of the leaf boxes.  1 <= n <=
+   RGX_MAX_GAUSSIANS (else RGX_ERR_INVALID_ARG / RGX_ERR_UNSUPPORTED).
+   Allocates device memory when the structure must grow (never during stream
+   capture).  The parameters are copied; the caller may change them
+   afterwards. */
 rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_build_opts *opts,
                          rgx_bvh **bvh, hipStream_t stream);
 void rgx_bvh_destroy(rgx_bvh *bvh);

@@ -173,8 +173,9 @@ int64_t rgx_bvh_size(const rgx_bvh *b) { return b ? b->n : 0; }
 rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_build_opts *opts,
                          rgx_bvh **bvh, hipStream_t stream) {
   if (!ctx || !g || !bvh) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
-  if (g->n <= 0 || g->n > (int64_t)INT32_MAX / 2)
-    return fail(ctx, RGX_ERR_INVALID_ARG, "n out of range");
+  if (g->n <= 0) return fail(ctx, RGX_ERR_INVALID_ARG, "n out of range");
+  if (g->n > RGX_MAX_GAUSSIANS)
+    return fail(ctx, RGX_ERR_UNSUPPORTED, "n above RGX_MAX_GAUSSIANS");
   if (g->sh_degree < 0 || g->sh_degree > 3)
     return fail(ctx, RGX_ERR_INVALID_ARG, "sh_degree must be 0..3");
   if (!g->means || !g->log_scales || !g->quats || !g->density || !g->sh)

@@ -72,7 +72,7 @@ __device__ __forceinline__ float box_entry(float lx, float ly, float lz, float h
 struct Gauss {
   float mx, my, mz, k2;
   float m[9];
-  float sig, l2sig;
+  float sig, l2sig, rad;   // rad: bounding-sphere radius of the ellipsoid
 };
 
 __device__ __forceinline__ Gauss load_gauss(const float *geom, int j) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ Gauss load_gauss(const float *geom, int j) {
   g.mx = a.x; g.my = a.y; g.mz = a.z; g.k2 = a.w;
   g.m[0] = b.x; g.m[1] = b.y; g.m[2] = b.z; g.m[3] = b.w;
   g.m[4] = c.x; g.m[5] = c.y; g.m[6] = c.z; g.m[7] = c.w;
-  g.m[8] = d.x; g.sig = d.y; g.l2sig = d.z;
+  g.m[8] = d.x; g.sig = d.y; g.l2sig = d.z; g.rad = d.w;
   return g;
 }
 
@@ -102,6 +102,19 @@ __device__ __forceinline__ void ray_local(const Gauss &g, const Ray &r, float &o
   dpx = fmaf(g.m[0], r.dx, fmaf(g.m[1], r.dy, g.m[2] * r.dz));
   dpy = fmaf(g.m[3], r.dx, fmaf(g.m[4], r.dy, g.m[5] * r.dz));
   dpz = fmaf(g.m[6], r.dx, fmaf(g.m[7], r.dy, g.m[8] * r.dz));
+}
+
+// Conservative pre-test of the chord test: can the ray meet the ellipsoid's
+// bounding sphere within [lo, hi]?  (The sphere's padding covers the FP32
+// chord ends.)
+__device__ __forceinline__ bool sphere_may_hit(const Gauss &g, const Ray &r, float lo, float hi) {
+  const float vx = g.mx - r.ox, vy = g.my - r.oy, vz = g.mz - r.oz;
+  const float tc = fmaf(vx, r.dx, fmaf(vy, r.dy, vz * r.dz));
+  const float cx = vy * r.dz - vz * r.dy, cy = vz * r.dx - vx * r.dz, cz = vx * r.dy - vy * r.dx;
+  const float rp = fmaf(fabsf(tc), 1e-5f, fmaf(g.rad, 1.001f, 1e-6f));
+  const float h2 = fmaf(rp, rp, -fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
+  const float h = __builtin_amdgcn_sqrtf(fmaxf(h2, 0.0f));
+  return h2 >= 0.0f && tc - h <= hi && tc + h >= lo;
 }
 
 __device__ __forceinline__ Chord chord(const Gauss &g, const Ray &r) {
@@ -229,11 +242,10 @@ __device__ __forceinline__ int pop_tile(int32_t *queue, int n_tiles, int home, i
 
 // Midpoint sample positions of a segment, t_k = o + (i0 + k + 1/2) dt: on the
 // fixed grid o = t_n and i0 = N_s * segment index, otherwise o = a, i0 = 0.
-// Evaluated on use (three registers instead of N_s).
+// Held as t_0 and dt, t_k = t_0 + k dt (two registers instead of N_s).
 struct Samples {
-  float o, dt;
-  int i0;
-  __device__ __forceinline__ float t(int k) const { return fmaf((float)(i0 + k) + 0.5f, dt, o); }
+  float t0, dt;
+  __device__ __forceinline__ float t(int k) const { return fmaf((float)k, dt, t0); }
 };
 
 // Eq. 5 with d_i = a (unit direction from the camera centre).
@@ -258,7 +270,7 @@ __device__ __forceinline__ void sample_weights(const Gauss &g, const Chord &c, c
                                                float *w) {
 #pragma unroll
   for (int k = 0; k < NS; k++) {
-    const float u = sp.t(k) - c.ts;
+    const float u = fmaf((float)k, sp.dt, sp.t0 - c.ts);
     const float q = fmaf(c.A * u, u, c.h2);
     const float e = __builtin_amdgcn_exp2f(fmaf(-q, kHalfLog2e, g.l2sig));
     w[k] = q <= g.k2 ? e : 0.0f;
@@ -273,9 +285,8 @@ __device__ __forceinline__ bool segment(const MarchOpts &op, bool grid, const Se
   a = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
   dt = op.adaptive ? adaptive_dt(op, a, T) : op.dt;
   b = grid ? fmaf((float)((ss.seg_i + 1) * NS), op.dt, tn) : fmaf((float)NS, dt, a);
-  sp.o = grid ? tn : a;
+  sp.t0 = grid ? fmaf((float)(ss.seg_i * NS) + 0.5f, dt, tn) : fmaf(0.5f, dt, a);
   sp.dt = dt;
-  sp.i0 = grid ? ss.seg_i * NS : 0;
   return b > a;
 }
 
@@ -486,7 +497,7 @@ __device__ __forceinline__ Gauss load_gauss_lane(const float *geom, int j) {
   g.mx = a.x; g.my = a.y; g.mz = a.z; g.k2 = a.w;
   g.m[0] = b.x; g.m[1] = b.y; g.m[2] = b.z; g.m[3] = b.w;
   g.m[4] = c.x; g.m[5] = c.y; g.m[6] = c.z; g.m[7] = c.w;
-  g.m[8] = d.x; g.sig = d.y; g.l2sig = d.z;
+  g.m[8] = d.x; g.sig = d.y; g.l2sig = d.z; g.rad = d.w;
   return g;
 }
 
@@ -564,26 +575,68 @@ __device__ __forceinline__ int compact_ring(WaveMem &M, int lane, int head, int 
   return base;
 }
 
-// Orders the list by Gaussian (Z) index: entries with index >= z1 are
-// dropped first, then each entry's rank (the number of smaller indices; the
-// indices are distinct) places its slot in M.u.order.  Returns the count.
-__device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int z1) {
-  count = compact_list(M, lane, count, z1);
-  int id[kListCap / 64], rank[kListCap / 64];
+// In-lane stage of the register bitonic sort: element 64q + lane is paired
+// with 64(q ^ JQ) + lane (the same lane).
+template <int JQ>
+__device__ __forceinline__ void bitonic_inlane(uint32_t (&key)[8], int k, int nq) {
 #pragma unroll
-  for (int q = 0; q < kListCap / 64; q++) {
-    id[q] = lane + 64 * q < count ? M.l_id[lane + 64 * q] : 0x7fffffff;
-    rank[q] = 0;
+  for (int q = 0; q < 8; q++) {
+    const int p = q ^ JQ;
+    if (p > q && p < nq) {
+      const bool up = ((64 * q) & k) == 0;
+      const uint32_t x = key[q], y = key[p];
+      const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
+      key[q] = up ? lo : hi;
+      key[p] = up ? hi : lo;
+    }
   }
-  for (int f = 0; f < count; f++) {
-    const int x = M.l_id[f];                 // same address in every lane: broadcast
+}
+
+// Orders the list by Gaussian (Z) index: entries with index >= z1 are
+// dropped first, then the keys (index << 9 | slot; indices are distinct and
+// below 2^23) are sorted by a bitonic network held in registers, element
+// 64q + lane in key[q] -- partners in other lanes are read with cross-lane
+// shuffles, partners in the same lane are registers.  The sorted slots go to
+// M.u.order.  Returns the count.
+__device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int z1) {
+  static_assert(kListCap <= 512, "sort keys hold a 9-bit slot");
+  count = compact_list(M, lane, count, z1);
+  int p2 = 64;
+  while (p2 < count) p2 <<= 1;
+  const int nq = p2 >> 6;
+  uint32_t key[8];
 #pragma unroll
-    for (int q = 0; q < kListCap / 64; q++) rank[q] += x < id[q] ? 1 : 0;
+  for (int q = 0; q < 8; q++) {
+    const int e = 64 * q + lane;
+    key[q] = e < count ? ((uint32_t)M.l_id[e] << 9) | (uint32_t)e : 0xffffffffu;
+  }
+  for (int k = 2; k <= p2; k <<= 1) {
+    for (int j = k >> 1; j >= 1; j >>= 1) {
+      if (j >= 64) {
+        if (j == 64) bitonic_inlane<1>(key, k, nq);
+        else if (j == 128) bitonic_inlane<2>(key, k, nq);
+        else bitonic_inlane<4>(key, k, nq);
+      } else {
+        const bool lower = (lane & j) == 0;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+          if (q < nq) {
+            const uint32_t x = key[q];
+            const uint32_t y = (uint32_t)__shfl_xor((int)x, j, 64);
+            const bool up = ((64 * q + lane) & k) == 0;
+            const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
+            key[q] = up == lower ? lo : hi;
+          }
+        }
+      }
+    }
   }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int q = 0; q < kListCap / 64; q++)
-    if (lane + 64 * q < count) M.u.order[rank[q]] = lane + 64 * q;
+  for (int q = 0; q < 8; q++) {
+    const int e = 64 * q + lane;
+    if (e < count) M.u.order[e] = (int)(key[q] & 511u);
+  }
   __builtin_amdgcn_wave_barrier();
   return count;
 }
@@ -887,7 +940,7 @@ __device__ __forceinline__ Gauss gauss_from_lane(const Gauss &v, int src) {
   g.mx = rl(v.mx); g.my = rl(v.my); g.mz = rl(v.mz); g.k2 = rl(v.k2);
 #pragma unroll
   for (int k = 0; k < 9; k++) g.m[k] = rl(v.m[k]);
-  g.sig = rl(v.sig); g.l2sig = rl(v.l2sig);
+  g.sig = rl(v.sig); g.l2sig = rl(v.l2sig); g.rad = rl(v.rad);
   return g;
 }
 
@@ -1097,7 +1150,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
           if (ls.error_flag) *ls.error_flag = 4;
         }
       }
-      if (!ss.alive) { sp.o = 0.0f; sp.dt = 0.0f; sp.i0 = 0; }
+      if (!ss.alive) { sp.t0 = 0.0f; sp.dt = 0.0f; }
       bool go;
       if (stats) cyc_t0 = clock64();
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
@@ -1114,11 +1167,11 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
 
       do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
                             [&](int j, const Gauss &g) {
-        const bool want = go;
+        const bool want = go && sphere_may_hit(g, r, lo, hi);
+        if (stats) cnt[ST_CAND]++;
         if (ballot(want) == 0) return;
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
-        if (stats) cnt[ST_CAND]++;
         if (ballot(hit) == 0) return;
         if (stats) cnt[ST_CAND_HIT]++;
         if (hit) {
@@ -1160,9 +1213,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         const float bmin = wave_min(empty ? b : kInf);
         for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active,
                            [&](int j, const Gauss &g) {
-          const bool want = empty;
+          const bool want = empty && sphere_may_hit(g, r, b, win.hi);
           if (ballot(want) == 0) return;
-            const Chord c = chord(g, r);
+          const Chord c = chord(g, r);
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
         });
       }
@@ -1293,7 +1346,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
           if (ls.error_flag) *ls.error_flag = 4;
         }
       }
-      if (!ss.alive) { sp.o = 0.0f; sp.dt = 0.0f; sp.i0 = 0; }
+      if (!ss.alive) { sp.t0 = 0.0f; sp.dt = 0.0f; }
       bool go;
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, false, ls.error_flag,
                     dummy_nodes, dummy_leaves, dummy_windows, go);
@@ -1307,7 +1360,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       // pass A: the forward's per-sample sums, in the forward's order
       do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
                             [&](int j, const Gauss &g) {
-        const bool want = go;
+        const bool want = go && sphere_may_hit(g, r, lo, hi);
         if (ballot(want) == 0) return;
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
@@ -1366,9 +1419,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
                      dummy_leaves, dummy_windows);
         do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
                               [&](int j, const Gauss &g) {
-          const bool want = any;
+          const bool want = any && sphere_may_hit(g, r, lo, hi);
           if (ballot(want) == 0) return;
-            float opx, opy, opz, dpx, dpy, dpz;
+          float opx, opy, opz, dpx, dpy, dpz;
           ray_local(g, r, opx, opy, opz, dpx, dpy, dpz);
           const Chord c = chord(g, r);
           const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
@@ -1384,7 +1437,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
             sample_weights<NS>(g, c, sp, wk);
 #pragma unroll
             for (int k = 0; k < NS; k++) {
-              const float u = sp.t(k) - c.ts;
+              const float u = fmaf((float)k, sp.dt, sp.t0 - c.ts);
               const float dw = sg[k] + W0[k] * cr + W1[k] * cg + W2[k] * cb;
               const float wdw = wk[k] * dw;
               ds += wdw;
@@ -1433,9 +1486,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         const float bmin = wave_min(empty ? b : kInf);
         for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active,
                            [&](int j, const Gauss &g) {
-          const bool want = empty;
+          const bool want = empty && sphere_may_hit(g, r, b, win.hi);
           if (ballot(want) == 0) return;
-            const Chord c = chord(g, r);
+          const Chord c = chord(g, r);
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
         });
       }
