@@ -104,19 +104,6 @@ __device__ __forceinline__ void ray_local(const Gauss &g, const Ray &r, float &o
   dpz = fmaf(g.m[6], r.dx, fmaf(g.m[7], r.dy, g.m[8] * r.dz));
 }
 
-// Conservative pre-test of the chord test: can the ray meet the ellipsoid's
-// bounding sphere within [lo, hi]?  (The sphere's padding covers the FP32
-// chord ends.)
-__device__ __forceinline__ bool sphere_may_hit(const Gauss &g, const Ray &r, float lo, float hi) {
-  const float vx = g.mx - r.ox, vy = g.my - r.oy, vz = g.mz - r.oz;
-  const float tc = fmaf(vx, r.dx, fmaf(vy, r.dy, vz * r.dz));
-  const float cx = vy * r.dz - vz * r.dy, cy = vz * r.dx - vx * r.dz, cz = vx * r.dy - vy * r.dx;
-  const float rp = fmaf(fabsf(tc), 1e-5f, fmaf(g.rad, 1.001f, 1e-6f));
-  const float h2 = fmaf(rp, rp, -fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
-  const float h = __builtin_amdgcn_sqrtf(fmaxf(h2, 0.0f));
-  return h2 >= 0.0f && tc - h <= hi && tc + h >= lo;
-}
-
 __device__ __forceinline__ Chord chord(const Gauss &g, const Ray &r) {
   float opx, opy, opz, dpx, dpy, dpz;
   ray_local(g, r, opx, opy, opz, dpx, dpy, dpz);
@@ -1167,7 +1154,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
 
       do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
                             [&](int j, const Gauss &g) {
-        const bool want = go && sphere_may_hit(g, r, lo, hi);
+        const bool want = go;
         if (stats) cnt[ST_CAND]++;
         if (ballot(want) == 0) return;
         const Chord c = chord(g, r);
@@ -1213,7 +1200,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         const float bmin = wave_min(empty ? b : kInf);
         for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active,
                            [&](int j, const Gauss &g) {
-          const bool want = empty && sphere_may_hit(g, r, b, win.hi);
+          const bool want = empty;
           if (ballot(want) == 0) return;
           const Chord c = chord(g, r);
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
@@ -1360,7 +1347,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       // pass A: the forward's per-sample sums, in the forward's order
       do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
                             [&](int j, const Gauss &g) {
-        const bool want = go && sphere_may_hit(g, r, lo, hi);
+        const bool want = go;
         if (ballot(want) == 0) return;
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
@@ -1419,7 +1406,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
                      dummy_leaves, dummy_windows);
         do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
                               [&](int j, const Gauss &g) {
-          const bool want = any && sphere_may_hit(g, r, lo, hi);
+          const bool want = any;
           if (ballot(want) == 0) return;
           float opx, opy, opz, dpx, dpy, dpz;
           ray_local(g, r, opx, opy, opz, dpx, dpy, dpz);
@@ -1486,7 +1473,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         const float bmin = wave_min(empty ? b : kInf);
         for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active,
                            [&](int j, const Gauss &g) {
-          const bool want = empty && sphere_may_hit(g, r, b, win.hi);
+          const bool want = empty;
           if (ballot(want) == 0) return;
           const Chord c = chord(g, r);
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
