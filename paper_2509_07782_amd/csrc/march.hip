@@ -73,7 +73,17 @@ struct Gauss {
   float mx, my, mz, k2;
   float m[9];
   float sig, l2sig, rad;   // rad: bounding-sphere radius of the ellipsoid
+  float ox, oy, oz;        // the camera centre in the local frame, M (o - mu) (with_origin)
 };
+
+// Fills the local-frame camera centre (shared by every ray of a wave).
+__device__ __forceinline__ Gauss with_origin(Gauss g, float ox, float oy, float oz) {
+  const float ex = ox - g.mx, ey = oy - g.my, ez = oz - g.mz;
+  g.ox = fmaf(g.m[0], ex, fmaf(g.m[1], ey, g.m[2] * ez));
+  g.oy = fmaf(g.m[3], ex, fmaf(g.m[4], ey, g.m[5] * ez));
+  g.oz = fmaf(g.m[6], ex, fmaf(g.m[7], ey, g.m[8] * ez));
+  return g;
+}
 
 __device__ __forceinline__ Gauss load_gauss(const float *geom, int j) {
   cfloat4p p = as_const4(geom) + 4 * j;
@@ -93,12 +103,12 @@ struct Chord {
   bool exists;
 };
 
+// The ray in the Gaussian's local frame (g carries the origin, with_origin).
 __device__ __forceinline__ void ray_local(const Gauss &g, const Ray &r, float &opx, float &opy,
                                           float &opz, float &dpx, float &dpy, float &dpz) {
-  const float ex = r.ox - g.mx, ey = r.oy - g.my, ez = r.oz - g.mz;
-  opx = fmaf(g.m[0], ex, fmaf(g.m[1], ey, g.m[2] * ez));
-  opy = fmaf(g.m[3], ex, fmaf(g.m[4], ey, g.m[5] * ez));
-  opz = fmaf(g.m[6], ex, fmaf(g.m[7], ey, g.m[8] * ez));
+  opx = g.ox;
+  opy = g.oy;
+  opz = g.oz;
   dpx = fmaf(g.m[0], r.dx, fmaf(g.m[1], r.dy, g.m[2] * r.dz));
   dpy = fmaf(g.m[3], r.dx, fmaf(g.m[4], r.dy, g.m[5] * r.dz));
   dpz = fmaf(g.m[6], r.dx, fmaf(g.m[7], r.dy, g.m[8] * r.dz));
@@ -371,7 +381,7 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
   float hi = ss.pending ? tf : -kInf;
   float best = kInf;
   auto leaf = [&](int j) {
-    const Gauss g = load_gauss(s.geom, j);
+    const Gauss g = with_origin(load_gauss(s.geom, j), r.ox, r.oy, r.oz);
     const Chord c = chord(g, r);
     if (c.exists && c.tin <= hi && c.tout >= lo) {
       best = fminf(best, fmaxf(c.tin, lo));
@@ -853,7 +863,7 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       if (stats && ballot(test)) {
         const int64_t c0 = clock64();
         // statistics only: AABB-only leaves per ray (box met, ellipsoid missed)
-        const Gauss g = load_gauss_lane(s.geom, test ? j : 0);
+        const Gauss g = with_origin(load_gauss_lane(s.geom, test ? j : 0), self.ox, self.oy, self.oz);
         const float *bx = s.aabb + 6 * (size_t)(test ? j : 0);
         for (uint64_t rem = rays; rem; rem &= rem - 1) {
           const int r = __builtin_ctzll(rem);
@@ -928,6 +938,7 @@ __device__ __forceinline__ Gauss gauss_from_lane(const Gauss &v, int src) {
 #pragma unroll
   for (int k = 0; k < 9; k++) g.m[k] = rl(v.m[k]);
   g.sig = rl(v.sig); g.l2sig = rl(v.l2sig); g.rad = rl(v.rad);
+  g.ox = rl(v.ox); g.oy = rl(v.oy); g.oz = rl(v.oz);
   return g;
 }
 
@@ -939,7 +950,8 @@ __device__ __forceinline__ Gauss gauss_from_lane(const Gauss &v, int src) {
 template <class Fn>
 __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, const WaveMem &M,
                                                    int count, int lane, float a_min, float b_max,
-                                                   int n_active, Fn &&fn) {
+                                                   int n_active, const Ray &r, Fn &&fn) {
+  const float ox = r.ox, oy = r.oy, oz = r.oz;
   if (kind == SRC_LIST) {
     for (int base = 0; base < count; base += 64) {
       const int e = base + lane;
@@ -952,14 +964,14 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
       }
       const uint64_t bits0 = ballot(keep);
       if (!bits0) continue;
-      const Gauss mine = load_gauss_lane(s.geom, keep ? id : 0);
+      const Gauss mine = with_origin(load_gauss_lane(s.geom, keep ? id : 0), ox, oy, oz);
       for (uint64_t bits = bits0; bits; bits &= bits - 1) {
         const int src = __builtin_ctzll(bits);
         fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src));
       }
     }
   } else {
-    for (int e = 0; e < n_active; e++) fn(e, load_gauss(s.geom, e));
+    for (int e = 0; e < n_active; e++) fn(e, with_origin(load_gauss(s.geom, e), ox, oy, oz));
   }
 }
 
@@ -1152,7 +1164,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
       int nhit = 0;
 
-      do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
+      do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
                             [&](int j, const Gauss &g) {
         const bool want = go;
         if (stats) cnt[ST_CAND]++;
@@ -1198,7 +1210,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       float best = kInf;
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active,
+        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r,
                            [&](int j, const Gauss &g) {
           const bool want = empty;
           if (ballot(want) == 0) return;
@@ -1345,7 +1357,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       int nhit = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
-      do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
+      do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
                             [&](int j, const Gauss &g) {
         const bool want = go;
         if (ballot(want) == 0) return;
@@ -1404,7 +1416,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         if (win.chunked)
           next_chunk(s, M, r, lane, n_active, any, a, b, 0, win, false, ls.error_flag, dummy_nodes,
                      dummy_leaves, dummy_windows);
-        do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active,
+        do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
                               [&](int j, const Gauss &g) {
           const bool want = any;
           if (ballot(want) == 0) return;
@@ -1471,7 +1483,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       float best = kInf;
       if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
-        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active,
+        for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r,
                            [&](int j, const Gauss &g) {
           const bool want = empty;
           if (ballot(want) == 0) return;
