@@ -453,7 +453,7 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
 
 constexpr int kRingCap = 256;    // frontier (stack) entries
 constexpr int kStageCap = 160;   // staged leaves; a round adds at most 2 per node
-constexpr int kListCap = 384;    // window list entries (multiple of 64)
+constexpr int kListCap = 512;    // window list entries (multiple of 64, at most 512)
 
 struct WaveMem {
   float rdx[64], rdy[64], rdz[64], rix[64], riy[64], riz[64], rlo[64], rhi[64];
