@@ -6,7 +6,7 @@
 // from a per-wave window list: for a depth window covering one or more
 // segments of every live lane, a node-parallel walk of the LBVH gathers the
 // Gaussians whose ellipsoid chord meets some lane's window, each with the
-// mask of those lanes and its extreme chord ends (see collect_window).  Every
+// mask of those lanes and its extreme chord ends (see trav_run).  Every
 // segment then runs over that list with a wave-uniform depth pre-check, so
 // one BVH walk serves several segments and its memory latency is spread over
 // 64 independent node fetches per round.  A window too large for the list is
@@ -457,13 +457,11 @@ constexpr int kListCap = 512;    // window list entries (multiple of 64, at most
 
 struct WaveMem {
   float rdx[64], rdy[64], rdz[64], rix[64], riy[64], riz[64], rlo[64], rhi[64];
-  union {
-    struct {                       // during collection
-      int32_t ring_id[kRingCap], ring_first[kRingCap];
-      int32_t st_id[kStageCap];
-    } c;
-    int32_t order[kListCap];       // afterwards: list slots in Z-index order
-  } u;
+  struct {                         // traversal state, kept while a collection is paused
+    int32_t ring_id[kRingCap], ring_first[kRingCap];
+    int32_t st_id[kStageCap];
+  } c;
+  int32_t order[kListCap];         // slots of the current chunk's entries, in Z-index order
   int32_t l_id[kListCap];
   float l_tin[kListCap], l_tout[kListCap];
   int32_t cnt_box[64];             // per-ray AABB-only leaf count (statistics)
@@ -555,16 +553,16 @@ __device__ __forceinline__ int compact_ring(WaveMem &M, int lane, int head, int 
     int id = 0, first = 0;
     bool keep = false;
     if (e < tail) {
-      id = M.u.c.ring_id[slot];
-      first = M.u.c.ring_first[slot];
+      id = M.c.ring_id[slot];
+      first = M.c.ring_first[slot];
       keep = first < z1;
     }
     __builtin_amdgcn_wave_barrier();
     const uint64_t b = ballot(keep);
     if (keep) {
       const int d = base + __popcll(b & below);
-      M.u.c.ring_id[d] = id;
-      M.u.c.ring_first[d] = first;
+      M.c.ring_id[d] = id;
+      M.c.ring_first[d] = first;
     }
     base += __popcll(b);
     __builtin_amdgcn_wave_barrier();
@@ -589,23 +587,25 @@ __device__ __forceinline__ void bitonic_inlane(uint32_t (&key)[8], int k, int nq
   }
 }
 
-// Orders the list by Gaussian (Z) index: entries with index >= z1 are
-// dropped first, then the keys (index << 9 | slot; indices are distinct and
-// below 2^23) are sorted by a bitonic network held in registers, element
-// 64q + lane in key[q] -- partners in other lanes are read with cross-lane
-// shuffles, partners in the same lane are registers.  The sorted slots go to
-// M.u.order.  Returns the count.
-__device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int z1) {
+// Orders the list entries with index below zc by Gaussian (Z) index (the
+// other entries stay in the list for a later chunk): the keys (index << 9 |
+// slot; indices are distinct and below 2^23) are sorted by a bitonic network
+// held in registers, element 64q + lane in key[q] -- partners in other lanes
+// are read with cross-lane shuffles, partners in the same lane are registers.
+// The sorted slots go to M.order.  Returns how many there are.
+__device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int zc) {
   static_assert(kListCap <= 512, "sort keys hold a 9-bit slot");
-  count = compact_list(M, lane, count, z1);
   int p2 = 64;
   while (p2 < count) p2 <<= 1;
   const int nq = p2 >> 6;
   uint32_t key[8];
+  int valid = 0;
 #pragma unroll
   for (int q = 0; q < 8; q++) {
     const int e = 64 * q + lane;
-    key[q] = e < count ? ((uint32_t)M.l_id[e] << 9) | (uint32_t)e : 0xffffffffu;
+    const int id = e < count ? M.l_id[e] : 0x7fffffff;
+    key[q] = id < zc ? ((uint32_t)id << 9) | (uint32_t)e : 0xffffffffu;
+    valid += __popcll(ballot(id < zc));
   }
   for (int k = 2; k <= p2; k <<= 1) {
     for (int j = k >> 1; j >= 1; j >>= 1) {
@@ -632,10 +632,10 @@ __device__ __forceinline__ int sort_list(WaveMem &M, int lane, int count, int z1
 #pragma unroll
   for (int q = 0; q < 8; q++) {
     const int e = 64 * q + lane;
-    if (e < count) M.u.order[e] = (int)(key[q] & 511u);
+    if (e < valid) M.order[e] = (int)(key[q] & 511u);
   }
   __builtin_amdgcn_wave_barrier();
-  return count;
+  return valid;
 }
 
 // The packet bound: apex o, unit axis u, half-angle (cos, sin) padded
@@ -731,21 +731,88 @@ __device__ __forceinline__ void support_bounds(const Cone &k, float vx, float vy
   *hi = c_hi + ext + pad;
 }
 
-// Collects the list for the rays in `rays` (windows in M.rlo / M.rhi) and
-// the Z range [z0, z1); z1 may be lowered.  Returns the number of list
-// entries, or -1 on a malformed tree (error flag set).
-__device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, int lane,
-                              uint64_t rays, int n_active, int z0, int &z1, bool stats,
-                              int32_t *err, int32_t &nodes_out, int32_t &leaves_out,
-                              int64_t *cyc_excl) {
-  if (n_active <= 0 || rays == 0 || z0 >= z1) return 0;
-  const int n_inner = n_active > 1 ? n_active - 1 : 1;
-  // stack S[0, sp): first leaf strictly decreasing towards the top S[sp-1]
-  int sp = 1, staged = 0, count = 0, visits = 0;
+// Wave-uniform state of a window collection.  The list holds the entries
+// found so far; the frontier stack and the staged leaves live in M.c.  A
+// collection ends either complete for [z0, z1) (z1 may have been lowered by a
+// cut) or paused: the list is full, and its entries below zp -- everything
+// below the smallest pending Z index -- form a complete chunk [z0, zp); after
+// that chunk, trav_advance drops those entries and trav_run resumes.
+struct Trav {
+  uint64_t rays;                   // lanes whose windows (M.rlo, M.rhi) are collected
+  int z0, z1, zp;
+  int sp, staged, count, visits;
+  bool paused;
+};
+
+__device__ __forceinline__ void trav_start(WaveMem &M, int lane, Trav &t, uint64_t rays, int z0,
+                                           int z1) {
+  t.rays = rays;
+  t.z0 = z0;
+  t.z1 = z1;
+  t.zp = z1;
+  t.sp = 1;
+  t.staged = 0;
+  t.count = 0;
+  t.visits = 0;
+  t.paused = false;
   if (lane == 0) {
-    M.u.c.ring_id[0] = 0;
-    M.u.c.ring_first[0] = 0;
+    M.c.ring_id[0] = 0;
+    M.c.ring_first[0] = 0;
   }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Drops the entries of a finished chunk [z0, zp) and moves z0 to zp.
+__device__ __forceinline__ void trav_advance(WaveMem &M, int lane, Trav &t) {
+  const uint64_t below = lanes_below(lane);
+  int base = 0;
+  for (int e0 = 0; e0 < t.count; e0 += 64) {
+    const int e = e0 + lane;
+    int id = 0;
+    float tin = 0.0f, tout = 0.0f;
+    bool keep = false;
+    if (e < t.count) {
+      id = M.l_id[e];
+      tin = M.l_tin[e];
+      tout = M.l_tout[e];
+      keep = id >= t.zp;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t b = ballot(keep);
+    if (keep) {
+      const int pos = base + __popcll(b & below);
+      M.l_id[pos] = id;
+      M.l_tin[pos] = tin;
+      M.l_tout[pos] = tout;
+    }
+    base += __popcll(b);
+    __builtin_amdgcn_wave_barrier();
+  }
+  t.count = base;
+  t.z0 = t.zp;
+  t.zp = t.z1;
+  t.paused = false;
+}
+
+// Runs (or resumes) the collection until it completes or pauses; sorts the
+// finished chunk's entries into M.order and returns their number, or -1 on
+// a malformed tree (error flag set).
+__device__ __forceinline__ int trav_run(const SceneDev &s, WaveMem &M, const Ray &self, int lane, Trav &t,
+                        int n_active, bool stats, int32_t *err, int32_t &nodes_out,
+                        int32_t &leaves_out, int64_t *cyc_excl) {
+  if (n_active <= 0 || t.rays == 0 || t.z0 >= t.z1) {
+    t.count = 0;
+    t.sp = 0;
+    t.staged = 0;
+    return 0;
+  }
+  const int n_inner = n_active > 1 ? n_active - 1 : 1;
+  const uint64_t rays = t.rays;
+  const int z0 = t.z0;
+  int z1 = t.z1;
+  // stack S[0, sp): first leaf strictly decreasing towards the top S[sp-1]
+  int sp = t.sp, staged = t.staged, count = t.count, visits = t.visits;
+  const int visits0 = visits;
   const Cone cone = packet_cone(M, self, lane, rays);
   const uint64_t below = lanes_below(lane);
   for (;;) {
@@ -756,12 +823,12 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       bool live = false;
       if (lane < n) {                            // lane 0 takes the top (lowest Z)
         const int slot = sp - 1 - lane;
-        id = M.u.c.ring_id[slot];
-        live = M.u.c.ring_first[slot] < z1;      // else cut off by a later z1
+        id = M.c.ring_id[slot];
+        live = M.c.ring_first[slot] < z1;      // else cut off by a later z1
       }
       sp -= n;
       visits += __popcll(ballot(live));
-      if (visits > n_inner) { if (err) *err = 2; return -1; }
+      if (visits > n_inner) { if (err) *err = 2; t.count = 0; t.sp = 0; t.staged = 0; return -1; }
       vf4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0}, c = {0, 0, 0, 0}, d = {0, 0, 0, 0};
       if (live) {
         const vf4 *np = reinterpret_cast<const vf4 *>(s.nodes) + 4 * id;
@@ -775,7 +842,7 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
                                 (cr != kNoChild && ((cr >= 0 ? cr >= n_inner : ~cr >= n_active) ||
                                                     !(0 <= nlo && nlo <= gamma && gamma < nhi &&
                                                       nhi < n_active))));
-      if (ballot(bad)) { if (err) *err = 3; return -1; }
+      if (ballot(bad)) { if (err) *err = 3; t.count = 0; t.sp = 0; t.staged = 0; return -1; }
       const bool inL = live && nlo < z1 && gamma >= z0;
       const bool inR = live && cr != kNoChild && gamma + 1 < z1 && nhi >= z0;
       const bool hL = inL && cone_box(cone, self, a.x, a.y, a.z, b.x, b.y, b.z);
@@ -793,7 +860,7 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
           for (int k = 0; k < kRingCap / 64; k++) {
             const int e = lane + 64 * k;
             ok[k] = e < sp;
-            v[k] = ok[k] ? M.u.c.ring_first[e] : 0;
+            v[k] = ok[k] ? M.c.ring_first[e] : 0;
           }
           v[kRingCap / 64] = nlo; ok[kRingCap / 64] = lI;
           v[kRingCap / 64 + 1] = gamma + 1; ok[kRingCap / 64 + 1] = rI;
@@ -810,13 +877,13 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         const int rank = __popcll(b1 & below) + __popcll(b2 & below);
         int pos = sp + tot - 1 - rank;
         if (lI) {
-          M.u.c.ring_id[pos] = cl;
-          M.u.c.ring_first[pos] = nlo;
+          M.c.ring_id[pos] = cl;
+          M.c.ring_first[pos] = nlo;
           pos--;
         }
         if (rI) {
-          M.u.c.ring_id[pos] = cr;
-          M.u.c.ring_first[pos] = gamma + 1;
+          M.c.ring_id[pos] = cr;
+          M.c.ring_first[pos] = gamma + 1;
         }
         sp += tot;
       }
@@ -825,8 +892,8 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
         const uint64_t b1 = ballot(lL || rL), b2 = ballot(lL && rL);
         const int tot = __popcll(b1) + __popcll(b2);
         int pos = staged + __popcll(b1 & below) + __popcll(b2 & below);
-        if (lL) M.u.c.st_id[pos++] = ~cl;
-        if (rL) M.u.c.st_id[pos] = ~cr;
+        if (lL) M.c.st_id[pos++] = ~cl;
+        if (rL) M.c.st_id[pos] = ~cr;
         staged += tot;
       }
     }
@@ -836,10 +903,29 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
     while (staged >= 64 || (done && staged > 0)) {
       __builtin_amdgcn_wave_barrier();
       const int k = min(64, staged);
+      if (count + k > kListCap) {
+        // the list may overflow: pause at the smallest pending Z index if
+        // the entries below it make a chunk
+        int zq = sp > 0 ? M.c.ring_first[sp - 1] : z1;
+        for (int e = lane; e < staged; e += 64) zq = min(zq, M.c.st_id[e]);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) zq = min(zq, __shfl_xor(zq, o, 64));
+        zq = min(__builtin_amdgcn_readfirstlane(zq), z1);
+        int nb = 0;
+        for (int e0 = 0; e0 < count; e0 += 64)
+          nb += __popcll(ballot(e0 + lane < count && M.l_id[e0 + lane] < zq));
+        if (nb > 0) {
+          t.sp = sp; t.staged = staged; t.count = count; t.visits = visits; t.z1 = z1;
+          t.zp = zq;
+          t.paused = true;
+          nodes_out += visits - visits0;
+          return sort_list(M, lane, count, zq);
+        }
+      }
       int j = 0;
       bool test = false;
       if (lane < k) {
-        j = M.u.c.st_id[lane];
+        j = M.c.st_id[lane];
         test = j < z1;
       }
       bool keep = false;
@@ -907,18 +993,21 @@ __device__ int collect_window(const SceneDev &s, WaveMem &M, const Ray &self, in
       int rid[2];
       for (int e = 0; e < 2; e++) {
         const int src = k + lane + 64 * e;
-        if (lane + 64 * e < rest) rid[e] = M.u.c.st_id[src];
+        if (lane + 64 * e < rest) rid[e] = M.c.st_id[src];
       }
       __builtin_amdgcn_wave_barrier();
       for (int e = 0; e < 2; e++) {
         const int dst = lane + 64 * e;
-        if (dst < rest) M.u.c.st_id[dst] = rid[e];
+        if (dst < rest) M.c.st_id[dst] = rid[e];
       }
       staged = rest;
     }
     if (done && staged == 0) break;
   }
-  nodes_out += visits;
+  nodes_out += visits - visits0;
+  t.sp = 0; t.staged = 0; t.count = count; t.visits = visits; t.z1 = z1;
+  t.zp = z1;
+  t.paused = false;
   return sort_list(M, lane, count, z1);
 }
 
@@ -958,7 +1047,7 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
       int id = 0;
       bool keep = false;
       if (e < count) {
-        const int o = M.u.order[e];
+        const int o = M.order[e];
         keep = !(M.l_tin[o] > b_max) && !(M.l_tout[o] < a_min);
         id = M.l_id[o];
       }
@@ -980,15 +1069,16 @@ struct Window {
   float len, len_min, len_max;   // uniform window length beyond the segment, and its bounds
   bool valid;                    // per lane: the current list covers this lane's later segments
   float hi;                      // per lane window end
-  int count;                     // uniform list size
+  int count;                     // uniform number of candidates in M.order
   int kind;                      // SourceKind of the current candidates
-  int z1;                        // uniform end of the list's Z range (n_active: complete)
   bool chunked;                  // uniform: this segment's candidates come in Z chunks
+  Trav t;                        // the collection behind the list
 };
 
 // Makes sure every live lane whose segment fits its window can march; when
 // no live lane can, collects a new window for all live lanes.  A window that
-// had to be cut in Z serves the current segment only, chunk by chunk.
+// could not be collected whole serves the current segment only, chunk by
+// chunk.
 __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts &op, WaveMem &M,
                                               const Ray &r, int lane, int n_active, bool alive,
                                               float a, float b, Window &w, bool stats,
@@ -1010,18 +1100,16 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
   const float hi = alive ? fmaxf(a + w.len, b) : -kInf;
   M.rlo[lane] = alive ? a : kInf;
   M.rhi[lane] = hi;
-  __builtin_amdgcn_wave_barrier();
   windows++;
-  int z1 = n_active;
-  const int cnt = collect_window(s, M, r, lane, rays, n_active, 0, z1, stats, err, nodes, leaves, cyc_excl);
+  trav_start(M, lane, w.t, rays, 0, n_active);
+  const int cnt = trav_run(s, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl);
   w.kind = SRC_LIST;
-  w.count = cnt > 0 ? cnt : 0;
-  w.z1 = cnt >= 0 ? z1 : n_active;     // a malformed tree ends the rays (error flag set)
-  w.chunked = w.z1 < n_active;
+  w.count = cnt > 0 ? cnt : 0;   // a malformed tree ends the rays (error flag set)
+  w.chunked = cnt >= 0 && (w.t.paused || w.t.z1 < n_active);
   if (!w.chunked) {
     w.valid = alive;
     w.hi = hi;
-    if (cnt < kListCap / 4) w.len = fminf(fmaxf(w.len * 1.5f, w.len_min), w.len_max);
+    if (w.t.count < kListCap / 4) w.len = fminf(fmaxf(w.len * 1.5f, w.len_min), w.len_max);
   } else {
     w.valid = false;
     w.len = w.len * 0.5f < w.len_min ? 0.0f : w.len * 0.5f;
@@ -1029,30 +1117,49 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
   fits = alive;
 }
 
-// In chunked mode, collects the candidates of the next Z chunk for the lanes
-// in `lanes` over their segments [a, b] (from Z index `z0`); false when the
-// segment's candidates are exhausted.
-__device__ __forceinline__ bool next_chunk(const SceneDev &s, WaveMem &M, const Ray &r, int lane,
-                                           int n_active, bool lanes, float a, float b, int z0,
-                                           Window &w, bool stats, int32_t *err, int32_t &nodes,
-                                           int32_t &leaves, int32_t &windows,
-                                           int64_t *cyc_excl = nullptr) {
-  if (!w.chunked || z0 >= n_active) return false;
+// Starts the chunks of the current segment again, for the lanes in `lanes`
+// over their segments [a, b].
+__device__ __forceinline__ void first_chunk(const SceneDev &s, WaveMem &M, const Ray &r, int lane,
+                                            int n_active, bool lanes, float a, float b, Window &w,
+                                            bool stats, int32_t *err, int32_t &nodes,
+                                            int32_t &leaves, int32_t &windows) {
   const uint64_t rays = ballot(lanes);
-  if (rays == 0) return false;
   M.rlo[lane] = lanes ? a : kInf;
   M.rhi[lane] = lanes ? b : -kInf;
-  __builtin_amdgcn_wave_barrier();
   windows++;
-  int z1 = n_active;
-  const int cnt = collect_window(s, M, r, lane, rays, n_active, z0, z1, stats, err, nodes, leaves, cyc_excl);
+  trav_start(M, lane, w.t, rays, 0, n_active);
+  const int cnt = trav_run(s, M, r, lane, w.t, n_active, stats, err, nodes, leaves, nullptr);
+  w.count = cnt > 0 ? cnt : 0;
+}
+
+// In chunked mode, moves to the candidates of the next Z chunk: resumes a
+// paused collection, or after a cut at z1 collects again from z1 for the
+// lanes in `lanes` over their segments [a, b].  False when the segment's
+// candidates are exhausted.
+__device__ __forceinline__ bool next_chunk(const SceneDev &s, WaveMem &M, const Ray &r, int lane,
+                                           int n_active, bool lanes, float a, float b, Window &w,
+                                           bool stats, int32_t *err, int32_t &nodes,
+                                           int32_t &leaves, int32_t &windows,
+                                           int64_t *cyc_excl = nullptr) {
+  if (!w.chunked) return false;
+  if (w.t.paused) {
+    trav_advance(M, lane, w.t);
+  } else {
+    if (w.t.z1 >= n_active) return false;
+    const uint64_t rays = ballot(lanes);
+    if (rays == 0) return false;
+    M.rlo[lane] = lanes ? a : kInf;
+    M.rhi[lane] = lanes ? b : -kInf;
+    windows++;
+    trav_start(M, lane, w.t, rays, w.t.z1, n_active);
+  }
+  const int cnt = trav_run(s, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl);
   if (cnt < 0) {
     w.count = 0;
-    w.z1 = n_active;
+    w.chunked = false;
     return false;
   }
   w.count = cnt;
-  w.z1 = z1;
   return true;
 }
 
@@ -1118,8 +1225,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
     win.hi = -kInf;
     win.count = 0;
     win.kind = SRC_LIST;
-    win.z1 = n_active;
     win.chunked = false;
+    win.t.paused = false;
+    win.t.z1 = n_active;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     int32_t cnt[kNStatUsed];
 #pragma unroll
@@ -1197,7 +1305,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         }
       }); while ([&] {
         if (stats) cyc_t0 = clock64();
-        const bool more = next_chunk(s, M, r, lane, n_active, go, a, b, win.z1, win, stats,
+        const bool more = next_chunk(s, M, r, lane, n_active, go, a, b, win, stats,
                                      ls.error_flag, cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS],
                                      stats ? &cyc_boxstat : nullptr);
         if (stats) cyc_collect += clock64() - cyc_t0;
@@ -1325,8 +1433,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
     win.hi = -kInf;
     win.count = 0;
     win.kind = SRC_LIST;
-    win.z1 = n_active;
     win.chunked = false;
+    win.t.paused = false;
+    win.t.z1 = n_active;
     int32_t dummy_nodes = 0, dummy_leaves = 0, dummy_windows = 0;
     float T = 1.0f;
 
@@ -1378,7 +1487,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
             W2[k] = fmaf(wk[k], cb, W2[k]);
           }
         }
-      }); while (next_chunk(s, M, r, lane, n_active, go, a, b, win.z1, win, false, ls.error_flag,
+      }); while (next_chunk(s, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
                             dummy_nodes, dummy_leaves, dummy_windows));
 
       // per-sample adjoints: dL/dsigma_k (into sg) and dL/dW_k (into W)
@@ -1414,8 +1523,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       if (ballot(any) != 0) {
         // a chunked segment starts its chunks again for the lanes that hit
         if (win.chunked)
-          next_chunk(s, M, r, lane, n_active, any, a, b, 0, win, false, ls.error_flag, dummy_nodes,
-                     dummy_leaves, dummy_windows);
+          first_chunk(s, M, r, lane, n_active, any, a, b, win, false, ls.error_flag, dummy_nodes,
+                      dummy_leaves, dummy_windows);
         do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
                               [&](int j, const Gauss &g) {
           const bool want = any;
@@ -1473,7 +1582,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
           const float mine = wave_reduce_slots(v, Y, dc0, dc1, dc2, lane);
           if (lane < 16 || (lane & 15) < op.sh_k)
             unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + lane, mine);
-        }); while (next_chunk(s, M, r, lane, n_active, any, a, b, win.z1, win, false, ls.error_flag,
+        }); while (next_chunk(s, M, r, lane, n_active, any, a, b, win, false, ls.error_flag,
                               dummy_nodes, dummy_leaves, dummy_windows));
       }
 
