@@ -5,15 +5,16 @@
 // lane marches its ray segment by segment (Alg. 1).  Candidate Gaussians come
 // from a per-wave window list: for a depth window covering one or more
 // segments of every live lane, a node-parallel walk of the LBVH gathers the
-// Gaussians whose ellipsoid chord meets some lane's window, each with the
-// mask of those lanes and its extreme chord ends (see trav_run).  Every
-// segment then runs over that list with a wave-uniform depth pre-check, so
-// one BVH walk serves several segments and its memory latency is spread over
-// 64 independent node fetches per round.  A window too large for the list is
-// cut by Z index and the segment proceeds chunk by chunk.  Geometry and colour
-// records of the Gaussian being evaluated are read at wave-uniform addresses
-// through the scalar cache.  Closest-hit restarts beyond the window use a
-// depth-first packet traversal, nearer child first.
+// Gaussians that may meet the packet of rays in its windows, each with
+// conservative depth bounds (see trav_run).  Every segment then runs over
+// that list with a wave-uniform depth pre-check, so one BVH walk serves
+// several segments and its memory latency is spread over 64 independent node
+// fetches per round.  A window too large for the list is processed in Z-index
+// chunks: the walk pauses when the list is full and resumes after the chunk.
+// The geometry of 64 list entries is fetched at once, one entry per lane, and
+// handed to each candidate with readlane; colour records are read at
+// wave-uniform addresses through the scalar cache.  Closest-hit restarts
+// beyond the window use a depth-first packet traversal, nearer child first.
 //
 // Every ray meets its Gaussians in Z-index order (window lists and their
 // chunks are sorted, brute force counts up), whatever packet, window, tile
@@ -687,13 +688,37 @@ __device__ __forceinline__ bool cone_sphere(const Cone &k, float vx, float vy, f
   return fmaf(perp, k.cs, -al * k.sn) <= pad;
 }
 
+// Conservative test of an AABB against the packet, on the box itself: the
+// depth shell through the box's exact distance range from the apex; the cone
+// through the box's extent across and along the axis (every box point p has
+// |p_perp| >= |c_perp| - r_w and p.u <= c.u + r_u, r_w and r_u the box's
+// supports along the unit perpendicular of its centre and along the axis).
 __device__ __forceinline__ bool cone_box(const Cone &k, const Ray &o, float lx, float ly, float lz,
                                          float hx, float hy, float hz) {
+  const float cx = fmaf(0.5f, lx + hx, -o.ox), cy = fmaf(0.5f, ly + hy, -o.oy),
+              cz = fmaf(0.5f, lz + hz, -o.oz);
   const float ex = 0.5f * (hx - lx), ey = 0.5f * (hy - ly), ez = 0.5f * (hz - lz);
-  float dlo, dhi;
-  return cone_sphere(k, fmaf(0.5f, lx + hx, -o.ox), fmaf(0.5f, ly + hy, -o.oy),
-                     fmaf(0.5f, lz + hz, -o.oz), sqrtf(fmaf(ex, ex, fmaf(ey, ey, ez * ez))), &dlo,
-                     &dhi);
+  const float ax = fabsf(cx), ay = fabsf(cy), az = fabsf(cz);
+  const float qx = fmaxf(ax - ex, 0.0f), qy = fmaxf(ay - ey, 0.0f), qz = fmaxf(az - ez, 0.0f);
+  const float fx = ax + ex, fy = ay + ey, fz = az + ez;
+  const float dmin = sqrtf(fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+  const float dmax = sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
+  const float pad = fmaf(dmax, 2e-5f, 1e-6f);
+  if (dmin - pad > k.t_hi || dmax + pad < k.t_lo) return false;
+  const float al = fmaf(cx, k.ux, fmaf(cy, k.uy, cz * k.uz));
+  const float ru = fmaf(ex, fabsf(k.ux), fmaf(ey, fabsf(k.uy), ez * fabsf(k.uz)));
+  if (al + ru + pad < 0.0f) return false;
+  if (!k.narrow) return true;
+  const float wx = cy * k.uz - cz * k.uy, wy = cz * k.ux - cx * k.uz, wz = cx * k.uy - cy * k.ux;
+  const float pw = sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz)));
+  // unit perpendicular of the centre: c - (c.u) u, normalised by |c x u|
+  const float px = fmaf(-al, k.ux, cx), py = fmaf(-al, k.uy, cy), pz = fmaf(-al, k.uz, cz);
+  const float rw = fmaf(ex, fabsf(px), fmaf(ey, fabsf(py), ez * fabsf(pz))) *
+                   __builtin_amdgcn_rcpf(fmaxf(pw, 1e-30f));
+  // margins: 1e-3 of the box extent for the rounding of the perpendicular
+  // direction, 2e-5 of the distance for the rest
+  const float slack = fmaf(rw, 1e-3f, pad);
+  return fmaf(pw - rw, k.cs, -(al + ru) * k.sn) <= slack;
 }
 
 // Depth bounds [lo, hi] of every ray of the packet inside one ellipsoid
