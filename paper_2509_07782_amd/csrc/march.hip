@@ -721,13 +721,14 @@ __device__ __forceinline__ bool cone_box(const Cone &k, const Ray &o, float lx, 
   return fmaf(pw - rw, k.cs, -(al + ru) * k.sn) <= slack;
 }
 
-// Depth bounds [lo, hi] of every ray of the packet inside one ellipsoid
+// Depth bounds [lo, hi] of every ray of the packet inside one ellipsoid, and
+// whether the ellipsoid can meet the cone at all (returned)
 // (centre v relative to the apex, size k, scales s, unit quaternion q): a
 // point o + t d of the ellipsoid satisfies |t - v.d| <= k |S R^T d| (its
 // support along d), v.d ranges over [|v| cos(phi + theta), |v| cos(phi - theta)]
 // for the angle phi between v and the axis, and |S R^T d| <= |S R^T u| +
 // max(s) |d - u| with |d - u| <= sin(theta) sqrt(2 / (1 + cos(theta))).
-__device__ __forceinline__ void support_bounds(const Cone &k, float vx, float vy, float vz,
+__device__ __forceinline__ bool support_bounds(const Cone &k, float vx, float vy, float vz,
                                                float kk, float sx, float sy, float sz, float qw,
                                                float qx, float qy, float qz, float *lo,
                                                float *hi) {
@@ -754,6 +755,20 @@ __device__ __forceinline__ void support_bounds(const Cone &k, float vx, float vy
   const float pad = fmaf(ext, 1e-3f, fmaf(d, 1e-5f, 1e-6f));
   *lo = c_lo - ext - pad;
   *hi = c_hi + ext + pad;
+  // the cone: every point p of the ellipsoid has |p_perp| >= perp - r_w and
+  // p.u <= al + r_u, with r_w, r_u its supports along the unit perpendicular
+  // of the centre and along the axis
+  if (!(perp > 0.0f)) return true;
+  const float ip = __builtin_amdgcn_rcpf(perp);
+  const float px = fmaf(-al, k.ux, vx) * ip, py = fmaf(-al, k.uy, vy) * ip,
+              pz = fmaf(-al, k.uz, vz) * ip;
+  const float y0 = sx * fmaf(R00, px, fmaf(R10, py, R20 * pz));
+  const float y1 = sy * fmaf(R01, px, fmaf(R11, py, R21 * pz));
+  const float y2 = sz * fmaf(R02, px, fmaf(R12, py, R22 * pz));
+  const float rw = kk * sqrtf(fmaf(y0, y0, fmaf(y1, y1, y2 * y2)));
+  const float ru = kk * sqrtf(fmaf(w0, w0, fmaf(w1, w1, w2 * w2)));
+  const float slack = fmaf(rw + ru, 1e-3f, fmaf(d, 2e-5f, 1e-6f));
+  return fmaf(perp - rw, k.cs, -(al + ru) * k.sn) <= slack;
 }
 
 // Wave-uniform state of a window collection.  The list holds the entries
@@ -964,11 +979,11 @@ __device__ __forceinline__ int trav_run(const SceneDev &s, WaveMem &M, const Ray
           const vf4 *ap = reinterpret_cast<const vf4 *>(s.aux) + 2 * j;
           const vf4 x0 = ap[0], x1 = ap[1];
           float lo, hi;
-          support_bounds(cone, vx, vy, vz, sqrtf(g0.w), x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z,
-                         &lo, &hi);
+          const bool in_cone = support_bounds(cone, vx, vy, vz, sqrtf(g0.w), x0.x, x0.y, x0.z,
+                                              x0.w, x1.x, x1.y, x1.z, &lo, &hi);
           tmin = fmaxf(tmin, lo);
           tmax = fminf(tmax, hi);
-          keep = tmin <= cone.t_hi && tmax >= cone.t_lo;
+          keep = in_cone && tmin <= cone.t_hi && tmax >= cone.t_lo;
         }
       }
       if (stats && ballot(test)) {
