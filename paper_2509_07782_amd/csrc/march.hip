@@ -323,6 +323,20 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
+// Minimum over the wave without LDS traffic: in-row DPP permutes (quad xor
+// 1, quad xor 2, half-row mirror, row mirror) leave each row's minimum in
+// every lane of the row; the four rows are then read back.
+__device__ __forceinline__ float wave_min_dpp(float v) {
+  v = fminf(v, dpp<0xb1>(v));
+  v = fminf(v, dpp<0x4e>(v));
+  v = fminf(v, dpp<0x141>(v));
+  v = fminf(v, dpp<0x140>(v));
+  auto rl = [&](int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+  };
+  return fminf(fminf(rl(0), rl(16)), fminf(rl(32), rl(48)));
+}
+
 template <int H, int CTRL>
 __device__ __forceinline__ void dpp_stage(float *x, int lane) {
   const bool up = (lane & H) != 0;
@@ -397,30 +411,58 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
     st.lane = __lane_id();
     st.sp = 0;
     int node = 0, visits = 0;
+    bool have = false;        // a..d already hold node's record (prefetched)
+    vf4 a = {0, 0, 0, 0}, b = a, c = a, d = a;
     for (;;) {
       if (node < 0) {
         if (st.sp == 0) break;
         const int v = st.pop();
         if (v < 0) { leaf(~v); continue; }
         node = v;
+        have = false;
       }
       if (++visits > n_inner) { if (err) *err = 2; break; }
-      cfloat4p np = as_const4(s.nodes) + 4 * node;
-      const vf4 a = np[0], b = np[1], c = np[2], d = np[3];
+      if (!have) {
+        cfloat4p np = as_const4(s.nodes) + 4 * node;
+        a = np[0]; b = np[1]; c = np[2]; d = np[3];
+      }
       const int cl = __float_as_int(a.w), cr = __float_as_int(b.w);
       const bool bad = (cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
                        (cr != kNoChild && (cr >= 0 ? cr >= n_inner : ~cr >= n_active));
       if (bad) { if (err) *err = 3; break; }
-      const float el = wave_min(box_entry(a.x, a.y, a.z, b.x, b.y, b.z, r, lo, hi));
-      const float er = cr != kNoChild ? wave_min(box_entry(c.x, c.y, c.z, d.x, d.y, d.z, r, lo, hi))
-                                      : kInf;
+      // prefetch the internal children's records (lane 0: left, lane 1:
+      // right) while this node's boxes are tested
+      const int lane_id = st.lane;
+      const int pid = lane_id == 0 ? cl : cr;
+      vf4 pa = {0, 0, 0, 0}, pb = pa, pc = pa, pd = pa;
+      if (lane_id < 2 && pid >= 0) {
+        const vf4 *q = reinterpret_cast<const vf4 *>(s.nodes) + 4 * pid;
+        pa = q[0]; pb = q[1]; pc = q[2]; pd = q[3];
+      }
+      const float el = wave_min_dpp(box_entry(a.x, a.y, a.z, b.x, b.y, b.z, r, lo, hi));
+      const float er = cr != kNoChild
+                           ? wave_min_dpp(box_entry(c.x, c.y, c.z, d.x, d.y, d.z, r, lo, hi))
+                           : kInf;
       const bool hl = el < kInf, hr = er < kInf;
       if (!hl && !hr) { node = -1; continue; }
       int near = cl, far = cr;
       if (hr && (!hl || er < el)) { near = cr; far = cl; }
       if (hl && hr && !st.push(far)) { if (err) *err = 1; break; }
-      if (near >= 0) node = near;
-      else { leaf(~near); node = -1; }
+      if (near >= 0) {
+        const int src = near == cl ? 0 : 1;
+        auto rl = [src](float x) {
+          return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), src));
+        };
+        a = vf4{rl(pa.x), rl(pa.y), rl(pa.z), rl(pa.w)};
+        b = vf4{rl(pb.x), rl(pb.y), rl(pb.z), rl(pb.w)};
+        c = vf4{rl(pc.x), rl(pc.y), rl(pc.z), rl(pc.w)};
+        d = vf4{rl(pd.x), rl(pd.y), rl(pd.z), rl(pd.w)};
+        node = near;
+        have = true;
+      } else {
+        leaf(~near);
+        node = -1;
+      }
     }
   }
   if (ss.pending) {
