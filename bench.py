@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1_000_000, help="Gaussians (workload: 1M)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=24)
+    ap.add_argument("--cpu-stride", type=int, default=17)
     ap.add_argument("--persistent", type=int, default=1)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
