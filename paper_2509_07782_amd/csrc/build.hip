@@ -250,28 +250,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 
 // ---------------------------------------------------------------------------
 // Z-ordered pack of the geometry, colour and AABB records of active Gaussians.
-__global__ __launch_bounds__(256) void k_pack(int64_t n, const int32_t *__restrict__ counters,
-                                              const uint32_t *__restrict__ perm,
-                                              const float *__restrict__ geom_user,
-                                              const float *__restrict__ aabb_user,
-                                              const float *__restrict__ aux_user,
-                                              const float *__restrict__ sh_user, int sh_k,
-                                              int col_stride, float *__restrict__ geom,
-                                              float *__restrict__ aabb, float *__restrict__ aux,
-                                              float *__restrict__ col) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int n_active = counters[0];
-  if (i >= n_active) return;
-  const int64_t src = perm[i];
-  const float4 *gs = reinterpret_cast<const float4 *>(geom_user + (size_t)kGeomFloats * src);
-  float4 *gd = reinterpret_cast<float4 *>(geom + (size_t)kGeomFloats * i);
-  for (int k = 0; k < 4; k++) gd[k] = gs[k];
-  for (int k = 0; k < 6; k++) aabb[6 * i + k] = aabb_user[6 * src + k];
-  for (int k = 0; k < kAuxFloats; k++) aux[kAuxFloats * i + k] = aux_user[kAuxFloats * src + k];
-  const float *cs = sh_user + (size_t)3 * sh_k * src;
-  float *cd = col + (size_t)col_stride * i;
-  for (int k = 0; k < 3 * sh_k; k++) cd[k] = cs[k];
-  for (int k = 3 * sh_k; k < col_stride; k++) cd[k] = 0.0f;
+// Z-ordered pack, one array at a time: dst row i = src row perm[i] (its
+// first src_cols floats, zero padding up to dst_stride).  One thread per
+// destination float, so the reads of a source row are contiguous and each
+// record's cache lines are fetched once.
+__global__ __launch_bounds__(256) void k_gather_rows(int64_t n, const int32_t *__restrict__ counters,
+                                                     const uint32_t *__restrict__ perm,
+                                                     const float *__restrict__ src, int src_stride,
+                                                     int src_cols, float *__restrict__ dst,
+                                                     int dst_stride) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = f / dst_stride;
+  const int k = (int)(f - i * dst_stride);
+  if (i >= n || i >= counters[0]) return;
+  dst[f] = k < src_cols ? src[(size_t)perm[i] * src_stride + k] : 0.0f;
 }
 
 // Node boxes without inter-thread synchronisation: a segment tree (heap
@@ -409,9 +401,17 @@ hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
     cur ^= 1;
   }
   *a.sorted_sel = cur;
-  k_pack<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.vals[cur], a.geom_user, a.aabb_user,
-                                       a.aux_user, a.sh, a.sh_k, a.col_stride, a.geom, a.aabb,
-                                       a.aux, a.col);
+  const uint32_t *perm = a.vals[cur];
+  k_gather_rows<<<nblk(n * kGeomFloats, 256), 256, 0, st>>>(n, a.counters, perm, a.geom_user,
+                                                            kGeomFloats, kGeomFloats, a.geom,
+                                                            kGeomFloats);
+  k_gather_rows<<<nblk(n * 6, 256), 256, 0, st>>>(n, a.counters, perm, a.aabb_user, 6, 6, a.aabb, 6);
+  k_gather_rows<<<nblk(n * kAuxFloats, 256), 256, 0, st>>>(n, a.counters, perm, a.aux_user,
+                                                           kAuxFloats, kAuxFloats, a.aux,
+                                                           kAuxFloats);
+  k_gather_rows<<<nblk(n * a.col_stride, 256), 256, 0, st>>>(n, a.counters, perm, a.sh,
+                                                             3 * a.sh_k, 3 * a.sh_k, a.col,
+                                                             a.col_stride);
   int64_t P = 1;
   while (P < n) P <<= 1;
   k_seg_leaves<<<nblk(P, 256), 256, 0, st>>>(P, a.counters, a.aabb, a.seg);
