@@ -78,7 +78,7 @@ struct rgx_bvh {
   int morton_bits = 21;
   int sorted_sel = 0;
   DevBuf geom_user, aabb_user, aux_user, aux, active, bounds, counters, keys0, keys1, vals0, vals1, hist, geom,
-      aabb, col, nodes, seg, parent, acc;
+      aabb, col, nodes, nodes4, seg, parent, acc;
 };
 
 static rgx_status fail(rgx_context *ctx, rgx_status s, const std::string &msg) {
@@ -163,7 +163,7 @@ void rgx_bvh_destroy(rgx_bvh *b) {
   if (!b) return;
   DevBuf *all[] = {&b->geom_user, &b->aabb_user, &b->aux_user, &b->aux, &b->active, &b->bounds, &b->counters, &b->keys0,
                    &b->keys1, &b->vals0, &b->vals1, &b->hist, &b->geom, &b->aabb, &b->col,
-                   &b->nodes, &b->seg, &b->parent, &b->acc};
+                   &b->nodes, &b->nodes4, &b->seg, &b->parent, &b->acc};
   for (DevBuf *d : all) release(*d);
   delete b;
 }
@@ -216,6 +216,7 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   ENS(aabb, (size_t)n * 6 * 4);
   ENS(col, (size_t)n * col_stride * 4);
   ENS(nodes, nodes_n * 16 * 4);
+  ENS(nodes4, nodes_n * kNode4Floats * 4);
   int64_t P = 1;
   while (P < n) P <<= 1;
   ENS(seg, (size_t)(2 * P) * 6 * 4);
@@ -248,6 +249,7 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   a.sorted_sel = &b->sorted_sel;
   a.geom = (float *)b->geom.p; a.aabb = (float *)b->aabb.p; a.col = (float *)b->col.p;
   a.nodes = (float *)b->nodes.p; a.seg = (float *)b->seg.p;
+  a.nodes4 = (float *)b->nodes4.p;
   a.parent = (int32_t *)b->parent.p;
   e = timed(ctx, RGX_KERN_BUILD, stream, [&] {
     hipError_t r = launch_build(a, stream);
@@ -271,6 +273,7 @@ static SceneDev scene_of(const rgx_bvh *b) {
   s.geom = (const float *)b->geom.p;
   s.col = (const float *)b->col.p;
   s.nodes = (const float *)b->nodes.p;
+  s.nodes4 = (const float *)b->nodes4.p;
   s.aabb = (const float *)b->aabb.p;
   s.counters = (const int32_t *)b->counters.p;
   s.perm = (const uint32_t *)(b->sorted_sel ? b->vals1.p : b->vals0.p);

@@ -378,6 +378,72 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
   nd[3] = make_float4(br[3], br[4], br[5], __int_as_float(hi));
 }
 
+// 4-wide nodes: every binary internal node at even depth (the root at depth
+// 0) gathers its children, and the children of those of them that are
+// internal (odd depth), into one record of up to 4 child boxes, links and
+// leaf ranges, in left-to-right (Z) order.  Records keep the binary node
+// index, so a link to an internal child is that child's binary index.
+__global__ __launch_bounds__(256) void k_bvh4(int64_t n_max, const int32_t *__restrict__ counters,
+                                              const float4 *__restrict__ nodes,
+                                              const int32_t *__restrict__ parent,
+                                              float *__restrict__ nodes4) {
+  const int n = counters[0];
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_inner = n > 1 ? n - 1 : 1;
+  if (tid >= n_max || n <= 0 || tid >= n_inner) return;
+  const int i = (int)tid;
+  int odd = 0;
+  for (int x = i, steps = 0; x > 0 && steps <= n; steps++) {
+    x = parent[x];
+    odd ^= 1;
+  }
+  if (odd) return;
+  float f[kNode4Floats];
+  for (int k = 0; k < 24; k++) f[k] = 0.0f;
+  for (int k = 0; k < 4; k++) {
+    f[24 + k] = __int_as_float(kNoChild);
+    f[28 + 2 * k] = __int_as_float(1);        // empty range
+    f[29 + 2 * k] = __int_as_float(0);
+  }
+  int m = 0;
+  auto add = [&](int link, float lx, float ly, float lz, float hx, float hy, float hz, int first,
+                 int last) {
+    f[6 * m + 0] = lx; f[6 * m + 1] = ly; f[6 * m + 2] = lz;
+    f[6 * m + 3] = hx; f[6 * m + 4] = hy; f[6 * m + 5] = hz;
+    f[24 + m] = __int_as_float(link);
+    f[28 + 2 * m] = __int_as_float(first);
+    f[29 + 2 * m] = __int_as_float(last);
+    m++;
+  };
+  const float4 a = nodes[4 * (size_t)i], b = nodes[4 * (size_t)i + 1], c = nodes[4 * (size_t)i + 2],
+               d = nodes[4 * (size_t)i + 3];
+  for (int side = 0; side < 2; side++) {
+    const int link = __float_as_int(side ? b.w : a.w);
+    if (link == kNoChild) continue;
+    const float4 lo = side ? c : a, hi = side ? d : b;
+    if (link < 0) {
+      add(link, lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, ~link, ~link);
+      continue;
+    }
+    const float4 a2 = nodes[4 * (size_t)link], b2 = nodes[4 * (size_t)link + 1],
+                 c2 = nodes[4 * (size_t)link + 2], d2 = nodes[4 * (size_t)link + 3];
+    for (int side2 = 0; side2 < 2; side2++) {
+      const int l2 = __float_as_int(side2 ? b2.w : a2.w);
+      if (l2 == kNoChild) continue;
+      const float4 lo2 = side2 ? c2 : a2, hi2 = side2 ? d2 : b2;
+      int first = ~l2, last = ~l2;
+      if (l2 >= 0) {
+        first = __float_as_int(nodes[4 * (size_t)l2 + 2].w);
+        last = __float_as_int(nodes[4 * (size_t)l2 + 3].w);
+      }
+      add(l2, lo2.x, lo2.y, lo2.z, hi2.x, hi2.y, hi2.z, first, last);
+    }
+  }
+  float4 *out = reinterpret_cast<float4 *>(nodes4 + (size_t)kNode4Floats * i);
+  for (int k = 0; k < kNode4Floats / 4; k++)
+    out[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+}
+
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -419,6 +485,8 @@ hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
     k_seg_level<<<nblk(lo, 256), 256, 0, st>>>(lo, 2 * lo, a.seg);
   k_lbvh_hierarchy<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.keys[cur], a.aabb, a.seg, P,
                                                  reinterpret_cast<float4 *>(a.nodes), a.parent);
+  k_bvh4<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, reinterpret_cast<const float4 *>(a.nodes),
+                                       a.parent, a.nodes4);
   return hipGetLastError();
 }
 

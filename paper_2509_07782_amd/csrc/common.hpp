@@ -11,6 +11,9 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxViewsPerLaunch = 24;    // view table travels as a kernel argument
 constexpr int kGeomFloats = 16;           // packed geometry record (64 B)
 constexpr int kAccFloats = 64;            // per-Gaussian gradient accumulator (256 B)
+// 4-wide node record: 4 child boxes (lo xyz, hi xyz), 4 child links (>= 0
+// 4-wide node, < 0 leaf ~j, kNoChild none), 4 leaf ranges (first, last).
+constexpr int kNode4Floats = 36;
 constexpr int kAuxFloats = 8;             // s.xyz, unit quaternion (w,x,y,z), |q|
 constexpr int32_t kNoChild = INT32_MIN;
 
