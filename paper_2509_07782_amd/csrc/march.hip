@@ -893,7 +893,7 @@ __device__ __forceinline__ int trav_run(const SceneDev &s, WaveMem &M, const Ray
   const uint64_t below = lanes_below(lane);
   for (;;) {
     __builtin_amdgcn_wave_barrier();
-    const int n = min(min(64, sp), (kStageCap - staged) >> 2);
+    const int n = min(min(64, sp), (kStageCap - staged) >> 1);
     if (n > 0) {
       int id = 0;
       bool live = false;
@@ -905,89 +905,71 @@ __device__ __forceinline__ int trav_run(const SceneDev &s, WaveMem &M, const Ray
       sp -= n;
       visits += __popcll(ballot(live));
       if (visits > n_inner) { if (err) *err = 2; t.count = 0; t.sp = 0; t.staged = 0; return -1; }
-      float f[kNode4Floats];
-      {
-        const vf4 *np = reinterpret_cast<const vf4 *>(s.nodes4) + (kNode4Floats / 4) * id;
-#pragma unroll
-        for (int q = 0; q < kNode4Floats / 4; q++) {
-          vf4 x = {0, 0, 0, 0};
-          if (live) x = np[q];
-          f[4 * q] = x.x; f[4 * q + 1] = x.y; f[4 * q + 2] = x.z; f[4 * q + 3] = x.w;
-        }
+      vf4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0}, c = {0, 0, 0, 0}, d = {0, 0, 0, 0};
+      if (live) {
+        const vf4 *np = reinterpret_cast<const vf4 *>(s.nodes) + 4 * id;
+        a = np[0]; b = np[1]; c = np[2]; d = np[3];
       }
-      // the 4 children, in Z order: internal ones go on the stack, leaves to staging
-      bool isI[4], isL[4];
-      int link[4], first[4];
-      bool bad = false;
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        link[k] = live ? __float_as_int(f[24 + k]) : kNoChild;
-        first[k] = __float_as_int(f[28 + 2 * k]);
-        const int last = __float_as_int(f[29 + 2 * k]);
-        const bool valid = link[k] != kNoChild;
-        bad = bad || (valid && ((link[k] >= 0 ? link[k] >= n_inner : ~link[k] >= n_active) ||
-                                !(0 <= first[k] && first[k] <= last && last < n_active)));
-        const bool in = valid && first[k] < z1 && last >= z0 &&
-                        cone_box(cone, self, f[6 * k], f[6 * k + 1], f[6 * k + 2], f[6 * k + 3],
-                                 f[6 * k + 4], f[6 * k + 5]);
-        isI[k] = in && link[k] >= 0;
-        isL[k] = in && link[k] < 0;
-      }
+      const int cl = live ? __float_as_int(a.w) : kNoChild;
+      const int cr = live ? __float_as_int(b.w) : kNoChild;
+      const int nlo = __float_as_int(c.w), nhi = __float_as_int(d.w);
+      const int gamma = cl < 0 ? ~cl : cl;       // left range [nlo, gamma], right [gamma+1, nhi]
+      const bool bad = live && ((cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
+                                (cr != kNoChild && ((cr >= 0 ? cr >= n_inner : ~cr >= n_active) ||
+                                                    !(0 <= nlo && nlo <= gamma && gamma < nhi &&
+                                                      nhi < n_active))));
       if (ballot(bad)) { if (err) *err = 3; t.count = 0; t.sp = 0; t.staged = 0; return -1; }
+      const bool inL = live && nlo < z1 && gamma >= z0;
+      const bool inR = live && cr != kNoChild && gamma + 1 < z1 && nhi >= z0;
+      const bool hL = inL && cone_box(cone, self, a.x, a.y, a.z, b.x, b.y, b.z);
+      const bool hR = inR && cone_box(cone, self, c.x, c.y, c.z, d.x, d.y, d.z);
+      // children, in lane order, left before right
+      bool lI = hL && cl >= 0, rI = hR && cr >= 0;
+      const bool lL = hL && cl < 0, rL = hR && cr < 0;
       {
-        int cI = 0;
-#pragma unroll
-        for (int k = 0; k < 4; k++) cI += isI[k] ? 1 : 0;
-        int tot = __popcll(ballot(cI & 1)) + 2 * __popcll(ballot(cI & 2)) + 4 * __popcll(ballot(cI & 4));
+        int tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
         if (sp + tot > kRingCap) {
           // frontier overflow: lower z1 to keep half the pending subtrees
-          int v[kRingCap / 64 + 4];
-          bool ok[kRingCap / 64 + 4];
+          int v[kRingCap / 64 + 2];
+          bool ok[kRingCap / 64 + 2];
 #pragma unroll
           for (int k = 0; k < kRingCap / 64; k++) {
             const int e = lane + 64 * k;
             ok[k] = e < sp;
             v[k] = ok[k] ? M.c.ring_first[e] : 0;
           }
-#pragma unroll
-          for (int k = 0; k < 4; k++) { v[kRingCap / 64 + k] = first[k]; ok[kRingCap / 64 + k] = isI[k]; }
+          v[kRingCap / 64] = nlo; ok[kRingCap / 64] = lI;
+          v[kRingCap / 64 + 1] = gamma + 1; ok[kRingCap / 64 + 1] = rI;
           z1 = select_cut(v, ok, z0 + 1, z1, kRingCap / 2);
           sp = compact_ring(M, lane, 0, sp, z1);
-          cI = 0;
-#pragma unroll
-          for (int k = 0; k < 4; k++) {
-            isI[k] = isI[k] && first[k] < z1;
-            isL[k] = isL[k] && ~link[k] < z1;
-            cI += isI[k] ? 1 : 0;
-          }
-          tot = __popcll(ballot(cI & 1)) + 2 * __popcll(ballot(cI & 2)) + 4 * __popcll(ballot(cI & 4));
+          lI = lI && nlo < z1;
+          rI = rI && gamma + 1 < z1;
+          tot = __popcll(ballot(lI)) + __popcll(ballot(rI));
         }
-        // the children are below every entry left on the stack and ascending
-        // in (lane, child) order; the r-th of them goes to S[sp + tot - 1 - r]
-        int rank = __popcll(ballot(cI & 1) & below) + 2 * __popcll(ballot(cI & 2) & below) +
-                   4 * __popcll(ballot(cI & 4) & below);
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-          if (isI[k]) {
-            const int pos = sp + tot - 1 - rank;
-            M.c.ring_id[pos] = link[k];
-            M.c.ring_first[pos] = first[k];
-            rank++;
-          }
+        // the children are below every entry left on the stack; in lane
+        // order, left before right, they are ascending, so the k-th of them
+        // goes to S[sp + tot - 1 - k]
+        const uint64_t b1 = ballot(lI || rI), b2 = ballot(lI && rI);
+        const int rank = __popcll(b1 & below) + __popcll(b2 & below);
+        int pos = sp + tot - 1 - rank;
+        if (lI) {
+          M.c.ring_id[pos] = cl;
+          M.c.ring_first[pos] = nlo;
+          pos--;
+        }
+        if (rI) {
+          M.c.ring_id[pos] = cr;
+          M.c.ring_first[pos] = gamma + 1;
         }
         sp += tot;
       }
       {
         // leaves past a lowered z1 are filtered when tested
-        int cL = 0;
-#pragma unroll
-        for (int k = 0; k < 4; k++) cL += isL[k] ? 1 : 0;
-        const int tot = __popcll(ballot(cL & 1)) + 2 * __popcll(ballot(cL & 2)) + 4 * __popcll(ballot(cL & 4));
-        int pos = staged + __popcll(ballot(cL & 1) & below) + 2 * __popcll(ballot(cL & 2) & below) +
-                  4 * __popcll(ballot(cL & 4) & below);
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-          if (isL[k]) M.c.st_id[pos++] = ~link[k];
+        const uint64_t b1 = ballot(lL || rL), b2 = ballot(lL && rL);
+        const int tot = __popcll(b1) + __popcll(b2);
+        int pos = staged + __popcll(b1 & below) + __popcll(b2 & below);
+        if (lL) M.c.st_id[pos++] = ~cl;
+        if (rL) M.c.st_id[pos] = ~cr;
         staged += tot;
       }
     }
