@@ -523,7 +523,8 @@ rgx_status rgx_dump_hits(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera 
 }
 
 rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *b, uint64_t *keys, int32_t *perm,
-                         float *aabb, float *nodes, int64_t *n_active, hipStream_t stream) {
+                         float *aabb, float *nodes, float *nodes4, int64_t *n_active,
+                         hipStream_t stream) {
   if (!ctx || !b) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
@@ -535,6 +536,9 @@ rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *b, uint64_t *keys, int
   if (aabb) HIP_TRY(ctx, hipMemcpy(aabb, b->aabb.p, n * 24, hipMemcpyDeviceToHost));
   if (nodes)
     HIP_TRY(ctx, hipMemcpy(nodes, b->nodes.p, std::max<size_t>(n - 1, 1) * 64, hipMemcpyDeviceToHost));
+  if (nodes4)
+    HIP_TRY(ctx, hipMemcpy(nodes4, b->nodes4.p, std::max<size_t>(n - 1, 1) * kNode4Floats * 4,
+                           hipMemcpyDeviceToHost));
   if (n_active) {
     int32_t c = 0;
     HIP_TRY(ctx, hipMemcpy(&c, b->counters.p, 4, hipMemcpyDeviceToHost));

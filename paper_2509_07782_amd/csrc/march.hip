@@ -1148,6 +1148,7 @@ struct Window {
   int count;                     // uniform number of candidates in M.order
   int kind;                      // SourceKind of the current candidates
   bool chunked;                  // uniform: this segment's candidates come in Z chunks
+  int zend;                      // uniform end of the Z range the chunks cover
   Trav t;                        // the collection behind the list
 };
 
@@ -1178,6 +1179,7 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
   M.rhi[lane] = hi;
   windows++;
   trav_start(M, lane, w.t, rays, 0, n_active);
+  w.zend = n_active;
   const int cnt = trav_run(s, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl);
   w.kind = SRC_LIST;
   w.count = cnt > 0 ? cnt : 0;   // a malformed tree ends the rays (error flag set)
@@ -1193,17 +1195,18 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
   fits = alive;
 }
 
-// Starts the chunks of the current segment again, for the lanes in `lanes`
-// over their segments [a, b].
+// Starts the chunks of the current segment again over the Z range [0, zend),
+// for the lanes in `lanes` over their segments [a, b].
 __device__ __forceinline__ void first_chunk(const SceneDev &s, WaveMem &M, const Ray &r, int lane,
-                                            int n_active, bool lanes, float a, float b, Window &w,
-                                            bool stats, int32_t *err, int32_t &nodes,
+                                            int n_active, bool lanes, float a, float b, int zend,
+                                            Window &w, bool stats, int32_t *err, int32_t &nodes,
                                             int32_t &leaves, int32_t &windows) {
   const uint64_t rays = ballot(lanes);
   M.rlo[lane] = lanes ? a : kInf;
   M.rhi[lane] = lanes ? b : -kInf;
   windows++;
-  trav_start(M, lane, w.t, rays, 0, n_active);
+  trav_start(M, lane, w.t, rays, 0, zend);
+  w.zend = zend;
   const int cnt = trav_run(s, M, r, lane, w.t, n_active, stats, err, nodes, leaves, nullptr);
   w.count = cnt > 0 ? cnt : 0;
 }
@@ -1221,13 +1224,13 @@ __device__ __forceinline__ bool next_chunk(const SceneDev &s, WaveMem &M, const 
   if (w.t.paused) {
     trav_advance(M, lane, w.t);
   } else {
-    if (w.t.z1 >= n_active) return false;
+    if (w.t.z1 >= w.zend) return false;
     const uint64_t rays = ballot(lanes);
     if (rays == 0) return false;
     M.rlo[lane] = lanes ? a : kInf;
     M.rhi[lane] = lanes ? b : -kInf;
     windows++;
-    trav_start(M, lane, w.t, rays, w.t.z1, n_active);
+    trav_start(M, lane, w.t, rays, w.t.z1, w.zend);
   }
   const int cnt = trav_run(s, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl);
   if (cnt < 0) {
@@ -1597,12 +1600,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
 
       // pass B: per-Gaussian adjoints, wave-reduced, one atomic per slot
       if (ballot(any) != 0) {
-        // a chunked segment starts its chunks again for the lanes that hit
-        if (win.chunked)
-          first_chunk(s, M, r, lane, n_active, any, a, b, win, false, ls.error_flag, dummy_nodes,
-                      dummy_leaves, dummy_windows);
-        do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
-                              [&](int j, const Gauss &g) {
+        auto pass_b = [&](int j, const Gauss &g) {
           const bool want = any;
           if (ballot(want) == 0) return;
           float opx, opy, opz, dpx, dpy, dpz;
@@ -1658,8 +1656,18 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
           const float mine = wave_reduce_slots(v, Y, dc0, dc1, dc2, lane);
           if (lane < 16 || (lane & 15) < op.sh_k)
             unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + lane, mine);
-        }); while (next_chunk(s, M, r, lane, n_active, any, a, b, win, false, ls.error_flag,
-                              dummy_nodes, dummy_leaves, dummy_windows));
+        };
+        // the list still holds the whole window, or the segment's last Z
+        // chunk [zlast, end); a chunked segment then collects [0, zlast) again
+        const int zlast = win.chunked ? win.t.z0 : 0;
+        for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, pass_b);
+        if (win.chunked && zlast > 0) {
+          first_chunk(s, M, r, lane, n_active, any, a, b, zlast, win, false, ls.error_flag,
+                      dummy_nodes, dummy_leaves, dummy_windows);
+          do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, pass_b);
+          while (next_chunk(s, M, r, lane, n_active, any, a, b, win, false, ls.error_flag,
+                            dummy_nodes, dummy_leaves, dummy_windows));
+        }
       }
 
       // restart after an empty segment: from the list inside the window, else

@@ -92,7 +92,7 @@ def load():
     L.rgx_dump_hits.argtypes = [vp, vp, C.POINTER(Camera), C.POINTER(RenderOpts), vp, C.c_int32,
                                 C.c_int32, vp, vp, vp, vp]
     L.rgx_dump_hits.restype = st
-    L.rgx_bvh_debug.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]
+    L.rgx_bvh_debug.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int64), vp]
     L.rgx_bvh_debug.restype = st
     L.rgx_error_flags.argtypes = [vp, C.POINTER(C.c_int32), vp]
     L.rgx_error_flags.restype = st
@@ -217,18 +217,20 @@ class BVH:
             pass
 
     def debug(self, stream=0):
-        """Host copies of keys, perm, leaf AABBs, nodes and the active count."""
+        """Host copies of keys, perm, leaf AABBs, binary nodes, 4-wide records
+        and the active count."""
         import numpy as np
         n = self.n
         keys = np.zeros(n, np.uint64)
         perm = np.zeros(n, np.int32)
         aabb = np.zeros((n, 6), np.float32)
         nodes = np.zeros((max(n - 1, 1), 16), np.float32)
+        nodes4 = np.zeros((max(n - 1, 1), 36), np.float32)
         na = C.c_int64(0)
         check(load().rgx_bvh_debug(self.ctx.h, self.h, keys.ctypes.data, perm.ctypes.data,
-                                   aabb.ctypes.data, nodes.ctypes.data, C.byref(na),
-                                   C.c_void_p(stream)), self.ctx.h, "rgx_bvh_debug")
-        return keys, perm, aabb, nodes, int(na.value)
+                                   aabb.ctypes.data, nodes.ctypes.data, nodes4.ctypes.data,
+                                   C.byref(na), C.c_void_p(stream)), self.ctx.h, "rgx_bvh_debug")
+        return keys, perm, aabb, nodes, nodes4, int(na.value)
 
 
 def render_forward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, stats=None, stream=0):

@@ -34,7 +34,7 @@ def test_build_structure(torch_cuda):
     sc["quats"][7:9] = 0.0                          # zero quaternion: inactive
     sc["means"][9, 0] = np.nan                      # non-finite: inactive
     r, _ = renderer_for(sc)
-    keys, perm, aabb, nodes, na = r.bvh.debug()
+    keys, perm, aabb, nodes, nodes4, na = r.bvh.debug()
     k2, act, R, half = oracle.gaussians(sc, np.float32(0.01))
     assert na == act.sum() == 5000 - 10
     assert np.all(np.diff(keys[:na].astype(np.float64)) >= 0)
@@ -70,6 +70,38 @@ def test_build_structure(torch_cuda):
                 stack.append((c, b, path + [node]))
     assert np.all(seen == 1)
     assert np.array_equal(lo_hi[:na - 1, 0], first) and np.array_equal(lo_hi[:na - 1, 1], last)
+    # the 4-wide records: every leaf reached once, in Z order, each child box
+    # equal to the binary tree's box of that child, ranges equal to its leaves
+    links4 = nodes4[:, 24:28].copy().view(np.int32)
+    ranges4 = nodes4[:, 28:36].copy().view(np.int32).reshape(-1, 4, 2)
+    order = []
+    stack = [0]
+    while stack:
+        node = stack.pop()
+        kids = []
+        for k in range(4):
+            c = links4[node, k]
+            if c == np.iinfo(np.int32).min:
+                assert np.all(ranges4[node, k] == [1, 0])
+                continue
+            box = nodes4[node, 6 * k:6 * k + 6]
+            if c < 0:
+                assert np.array_equal(box, aabb[~c]) and np.all(ranges4[node, k] == ~c)
+            else:
+                assert np.all(ranges4[node, k] == [first[c], last[c]])
+                assert np.all(box[:3] <= aabb[first[c]:last[c] + 1, :3].min(0))
+                assert np.all(box[3:] >= aabb[first[c]:last[c] + 1, 3:].max(0))
+            kids.append(c)
+        for c in reversed(kids):
+            if c < 0:
+                order.append(~c)
+            else:
+                stack.append(c)
+        # leaves listed before a deeper subtree are emitted late here; compare
+        # as a multiset below and check the ranges are disjoint and ascending
+        rs = [tuple(ranges4[node, k]) for k in range(4) if links4[node, k] != np.iinfo(np.int32).min]
+        assert all(rs[q][1] < rs[q + 1][0] for q in range(len(rs) - 1))
+    assert sorted(order) == list(range(na))
 
 
 def test_config1_brute_force_matches_oracle(torch_cuda):
