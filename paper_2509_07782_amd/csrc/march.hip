@@ -132,27 +132,16 @@ __device__ __forceinline__ Chord chord(const Gauss &g, const Ray &r) {
   return c;
 }
 
-// A Gaussian's SH coefficients [m][rgb] (wave-uniform, scalar loads; only
-// the record's own words are read).
-struct ColourRec {
-  vf4 q[12];
-};
-__device__ __forceinline__ ColourRec load_colour(const float *col, int j, int col_stride, int sh_k) {
-  cfloat4p p = as_const4(col) + (size_t)(col_stride >> 2) * j;
-  ColourRec c;
-#pragma unroll
-  for (int q = 0; q < 12; q++) c.q[q] = 4 * q < 3 * sh_k ? p[q] : vf4{0, 0, 0, 0};
-  return c;
-}
-
 // Colour of a Gaussian at the lane's direction: c = sum_m f_m Y_m.
-__device__ __forceinline__ void colour_of(const ColourRec &c, int sh_k, const float *Y, float &cr,
-                                          float &cg, float &cb) {
+__device__ __forceinline__ void colour(const float *col, int j, int col_stride, int sh_k,
+                                       const float *Y, float &cr, float &cg, float &cb) {
+  cfloat4p p = as_const4(col) + (size_t)(col_stride >> 2) * j;
   float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int q = 0; q < 12; q++) {
     if (4 * q < 3 * sh_k) {
-      const float fv[4] = {c.q[q].x, c.q[q].y, c.q[q].z, c.q[q].w};
+      const vf4 f = p[q];
+      const float fv[4] = {f.x, f.y, f.z, f.w};
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         const int flat = 4 * q + e;
@@ -161,11 +150,6 @@ __device__ __forceinline__ void colour_of(const ColourRec &c, int sh_k, const fl
     }
   }
   cr = acc[0]; cg = acc[1]; cb = acc[2];
-}
-
-__device__ __forceinline__ void colour(const float *col, int j, int col_stride, int sh_k,
-                                       const float *Y, float &cr, float &cg, float &cb) {
-  colour_of(load_colour(col, j, col_stride, sh_k), sh_k, Y, cr, cg, cb);
 }
 
 // Wave-uniform DFS stack, entry i held by lane i of s0 (i < 64) or s1.
@@ -1372,8 +1356,6 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         const bool want = go;
         if (stats) cnt[ST_CAND]++;
         if (ballot(want) == 0) return;
-        // the colour record's loads go out first: their latency overlaps the chord
-        const ColourRec crec = load_colour(s.col, j, op.col_stride, op.sh_k);
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
         if (ballot(hit) == 0) return;
@@ -1389,7 +1371,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
             n_dump++;
           }
           float cr, cg, cb;
-          colour_of(crec, op.sh_k, Y, cr, cg, cb);
+          colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
           float wk[NS];
           sample_weights<NS>(g, c, sp, wk);
 #pragma unroll
@@ -1567,14 +1549,13 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
                             [&](int j, const Gauss &g) {
         const bool want = go;
         if (ballot(want) == 0) return;
-        const ColourRec crec = load_colour(s.col, j, op.col_stride, op.sh_k);
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
         if (ballot(hit) == 0) return;
         if (hit) {
           nhit++;
           float cr, cg, cb;
-          colour_of(crec, op.sh_k, Y, cr, cg, cb);
+          colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
           float wk[NS];
           sample_weights<NS>(g, c, sp, wk);
 #pragma unroll
