@@ -205,6 +205,17 @@ rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *bvh, uint64_t *keys, i
    flags[0] != 0 means a traversal exceeded its stack (results invalid). */
 rgx_status rgx_error_flags(rgx_context *ctx, int32_t *flags /*host*/, hipStream_t stream);
 
+/* Isotropic scale loss (Sec. 3.4, Eq. 8, with the volume-ratio bound of
+   Eq. 7 / Eq. 9): for s = exp(log_scales[i]) the bound is
+   r_i = 2/(pi sqrt 3) (sum_j s_ij^2)^(3/2) / prod_j s_ij, and
+   L = (1/n) sum_i (max(r_i, r0) - r0).  Writes L to *loss (device float) and
+   dL/d(log_scales) to grad [n,3] (device; accumulate != 0 adds into it).
+   log_scales is [n,3] device float32, 1 <= n <= RGX_MAX_GAUSSIANS, r0 > 0.
+   The reduction is deterministic.  Allocates a small per-context workspace
+   the first time (and when n grows). */
+rgx_status rgx_isotropic_loss(rgx_context *ctx, int64_t n, const float *log_scales, float r0,
+                              float *loss, float *grad, int32_t accumulate, hipStream_t stream);
+
 /* Optional kernel timing, for measurement.  While enabled, every launch made
    by rgx_build_bvh, rgx_render_forward and rgx_render_backward is bracketed
    by two HIP events recorded on the caller's stream (so the interval is that

@@ -44,6 +44,8 @@ struct rgx_context {
   std::vector<hipEvent_t> ev;       // 2 per recorded launch, reused after a reset
   std::vector<int> ev_kind;         // RGX_KERN_* of each recorded launch
   size_t ev_used = 0;
+  double *partial = nullptr;        // per-block partial sums of rgx_isotropic_loss
+  int64_t partial_cap = 0;
 };
 
 // Records hipEvents on `stream` around `launch` when timing is enabled.
@@ -156,6 +158,7 @@ void rgx_destroy(rgx_context *ctx) {
   for (auto &kv : ctx->tile_orders) (void)hipFree(kv.second);
   if (ctx->queue) (void)hipFree(ctx->queue);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->partial) (void)hipFree(ctx->partial);
   delete ctx;
 }
 
@@ -567,6 +570,24 @@ rgx_status rgx_kernel_times(rgx_context *ctx, double *ms, int64_t *launches, int
     launches[k] += 1;
   }
   if (reset) ctx->ev_used = 0;
+  return RGX_OK;
+}
+
+rgx_status rgx_isotropic_loss(rgx_context *ctx, int64_t n, const float *log_scales, float r0,
+                              float *loss, float *grad, int32_t accumulate, hipStream_t stream) {
+  if (!ctx || !log_scales || !loss || !grad) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  if (n <= 0 || n > RGX_MAX_GAUSSIANS) return fail(ctx, RGX_ERR_INVALID_ARG, "n out of range");
+  if (!(r0 > 0.0f) || !std::isfinite(r0)) return fail(ctx, RGX_ERR_INVALID_ARG, "r0 must be > 0");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int64_t nb = iso_blocks(n);
+  if (nb > ctx->partial_cap) {
+    if (ctx->partial) (void)hipFree(ctx->partial);
+    ctx->partial = nullptr;
+    ctx->partial_cap = 0;
+    HIP_TRY(ctx, hipMalloc((void **)&ctx->partial, (size_t)nb * sizeof(double)));
+    ctx->partial_cap = nb;
+  }
+  HIP_TRY(ctx, launch_isotropic_loss(n, log_scales, r0, loss, grad, accumulate, ctx->partial, stream));
   return RGX_OK;
 }
 

@@ -28,6 +28,9 @@ struct BuildArgs {
   int32_t *parent;
 };
 hipError_t launch_build(const BuildArgs &a, hipStream_t st);
+int64_t iso_blocks(int64_t n);
+hipError_t launch_isotropic_loss(int64_t n, const float *log_scales, float r0, float *loss,
+                                 float *grad, int accumulate, double *partial, hipStream_t st);
 
 struct SceneDev {
   const float *geom;          // [n,16]

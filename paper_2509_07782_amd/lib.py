@@ -56,7 +56,7 @@ class Grads(C.Structure):
 
 EXPORTS = ("rgx_create", "rgx_destroy", "rgx_build_bvh", "rgx_bvh_destroy", "rgx_bvh_size",
            "rgx_render_forward", "rgx_render_backward", "rgx_dump_hits", "rgx_bvh_debug",
-           "rgx_error_flags", "rgx_set_kernel_timing", "rgx_kernel_times",
+           "rgx_error_flags", "rgx_set_kernel_timing", "rgx_kernel_times", "rgx_isotropic_loss",
            "rgx_status_string", "rgx_last_error")
 
 KERNEL_KINDS = ("build", "forward", "backward", "finalize")   # RGX_KERN_* order
@@ -96,6 +96,8 @@ def load():
     L.rgx_bvh_debug.restype = st
     L.rgx_error_flags.argtypes = [vp, C.POINTER(C.c_int32), vp]
     L.rgx_error_flags.restype = st
+    L.rgx_isotropic_loss.argtypes = [vp, C.c_int64, vp, C.c_float, vp, vp, C.c_int32, vp]
+    L.rgx_isotropic_loss.restype = st
     L.rgx_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.rgx_set_kernel_timing.restype = st
     L.rgx_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
@@ -231,6 +233,14 @@ class BVH:
                                    aabb.ctypes.data, nodes.ctypes.data, nodes4.ctypes.data,
                                    C.byref(na), C.c_void_p(stream)), self.ctx.h, "rgx_bvh_debug")
         return keys, perm, aabb, nodes, nodes4, int(na.value)
+
+
+def isotropic_loss(ctx: Context, log_scales, r0, loss, grad, accumulate=False, stream=0):
+    """Loss (device scalar) and dL/d(log_scales) of the isotropic scale loss."""
+    check(load().rgx_isotropic_loss(ctx.h, int(log_scales.shape[0]), log_scales.data_ptr(),
+                                    float(r0), loss.data_ptr(), grad.data_ptr(),
+                                    int(bool(accumulate)), C.c_void_p(stream)),
+          ctx.h, "rgx_isotropic_loss")
 
 
 def render_forward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, stats=None, stream=0):

@@ -162,3 +162,26 @@ class TrainStep:
     def replay(self):
         self.graph.replay()
         return self.loss
+
+
+class IsotropicLossFunction(torch.autograd.Function):
+    """Isotropic scale loss (library kernel): mean over Gaussians of
+    max(r, r0) - r0, r the AABB/ellipsoid volume-ratio bound of the scales."""
+
+    @staticmethod
+    def forward(ctx, log_scales, renderer: Renderer, r0: float):
+        ls = log_scales.contiguous()
+        loss = torch.empty((), device=ls.device, dtype=torch.float32)
+        grad = torch.empty_like(ls)
+        lib.isotropic_loss(renderer.ctx, ls, r0, loss, grad, False, _stream())
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return grad * g, None, None
+
+
+def isotropic_loss(log_scales, renderer: Renderer, r0: float = 10.0):
+    return IsotropicLossFunction.apply(log_scales, renderer, r0)
