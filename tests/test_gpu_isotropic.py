@@ -12,6 +12,14 @@ from helpers import renderer_for
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
 def _ratio(ls):
     return og.ratio_bound(np.exp(np.asarray(ls, np.float64)))
 
