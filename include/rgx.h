@@ -107,6 +107,15 @@ typedef struct {
 typedef struct {             /* gradient outputs, user order, float32 */
   float *means, *log_scales, *quats, *density, *sh;  /* [n,3] [n,3] [n,4] [n] [n,K,3] */
   int32_t accumulate;        /* 0: overwrite, 1: add into the buffers */
+  /* Densification statistic of Sec. 3.5 (Eq. 12), nullable: for each view v
+     of the call, densify[i] += alpha_v |dL_v/dmu_i| with alpha_v =
+     |mu_i - o_v| / f_v (o_v the camera centre, f_v = fx of view v) and
+     L_v the loss restricted to view v's pixels; densify_views[i] += 1 when
+     that gradient is non-zero.  Both are added to (never cleared), so the
+     caller keeps the running sums between densification steps.  When
+     densify is set the views are marched one at a time. */
+  float *densify;            /* [n] */
+  int32_t *densify_views;    /* [n], required with densify */
 } rgx_grads;
 
 /* per-ray statistics written by rgx_render_forward when `stats` is given */

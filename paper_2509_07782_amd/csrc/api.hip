@@ -80,7 +80,7 @@ struct rgx_bvh {
   int morton_bits = 21;
   int sorted_sel = 0;
   DevBuf geom_user, aabb_user, aux_user, aux, active, bounds, counters, keys0, keys1, vals0, vals1, hist, geom,
-      aabb, col, nodes, nodes4, seg, parent, acc;
+      aabb, col, nodes, nodes4, seg, parent, acc, zprev;
 };
 
 static rgx_status fail(rgx_context *ctx, rgx_status s, const std::string &msg) {
@@ -166,7 +166,7 @@ void rgx_bvh_destroy(rgx_bvh *b) {
   if (!b) return;
   DevBuf *all[] = {&b->geom_user, &b->aabb_user, &b->aux_user, &b->aux, &b->active, &b->bounds, &b->counters, &b->keys0,
                    &b->keys1, &b->vals0, &b->vals1, &b->hist, &b->geom, &b->aabb, &b->col,
-                   &b->nodes, &b->nodes4, &b->seg, &b->parent, &b->acc};
+                   &b->nodes, &b->nodes4, &b->seg, &b->parent, &b->acc, &b->zprev};
   for (DevBuf *d : all) release(*d);
   delete b;
 }
@@ -375,9 +375,10 @@ static rgx_status tile_order(rgx_context *ctx, int W, int H, int tw, int th, con
 
 // Split the views into launches of at most kMaxViewsPerLaunch.
 static rgx_status view_tables(rgx_context *ctx, const rgx_camera *cams, int n_views,
-                              const MarchOpts &m, std::vector<ViewTable> &tabs) {
+                              const MarchOpts &m, std::vector<ViewTable> &tabs,
+                              int64_t ray0 = 0) {
   if (!cams || n_views <= 0) return fail(ctx, RGX_ERR_INVALID_ARG, "no views");
-  int64_t ray = 0;
+  int64_t ray = ray0;
   for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPerLaunch) {
     ViewTable t;
     memset(&t, 0, sizeof t);
@@ -480,10 +481,33 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
   in.grad_rgb = grad_rgb;
   in.grad_T = grad_T;
   in.acc = (float *)bvh->acc.p;
-  for (const ViewTable &t : tabs) {
-    if (t.n_tiles == 0) continue;
-    HIP_TRY(ctx, timed(ctx, RGX_KERN_BACKWARD, stream,
-                       [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles), stream); }));
+  if (!grads->densify) {
+    for (const ViewTable &t : tabs) {
+      if (t.n_tiles == 0) continue;
+      HIP_TRY(ctx, timed(ctx, RGX_KERN_BACKWARD, stream,
+                         [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles), stream); }));
+    }
+  } else {
+    // one view at a time: each view's mean gradient is the change of the
+    // accumulated mean slots, turned into the densification statistic
+    if (!grads->densify_views) return fail(ctx, RGX_ERR_INVALID_ARG, "densify needs densify_views");
+    rgx_bvh *mb = const_cast<rgx_bvh *>(bvh);
+    HIP_TRY(ctx, ensure(mb->zprev, (size_t)bvh->n * 3 * sizeof(float)));
+    HIP_TRY(ctx, launch_fill(mb->zprev.p, bvh->n * 3, 0u, stream));
+    int64_t ray0 = 0;
+    for (int v = 0; v < n_views; v++) {
+      std::vector<ViewTable> one;
+      if ((s = view_tables(ctx, cams + v, 1, m, one, ray0)) != RGX_OK) return s;
+      ray0 += (int64_t)cams[v].width * cams[v].height;
+      for (const ViewTable &t : one) {
+        if (t.n_tiles == 0) continue;
+        HIP_TRY(ctx, timed(ctx, RGX_KERN_BACKWARD, stream,
+                           [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles), stream); }));
+      }
+      const float *c2w = cams[v].cam_to_world;
+      HIP_TRY(ctx, launch_densify(sd, (const float *)bvh->acc.p, (float *)mb->zprev.p, c2w[3], c2w[7],
+                                  c2w[11], cams[v].fx, grads->densify, grads->densify_views, stream));
+    }
   }
   HIP_TRY(ctx, timed(ctx, RGX_KERN_FINALIZE, stream, [&] {
     return launch_finalize_grads(sd, bvh->sh_k, (float *)bvh->acc.p, grads->means, grads->log_scales,

@@ -72,6 +72,8 @@ hipError_t launch_backward(const SceneDev &s, const ViewTable &vt, const MarchOp
 hipError_t launch_finalize_grads(const SceneDev &s, int sh_k, float *acc, float *g_means,
                                  float *g_log_scales, float *g_quats, float *g_density,
                                  float *g_sh, int accumulate, hipStream_t st);
+hipError_t launch_densify(const SceneDev &s, const float *acc, float *zprev, float ox, float oy,
+                          float oz, float focal, float *densify, int32_t *views, hipStream_t st);
 hipError_t launch_fill(void *p, int64_t n_words, uint32_t value, hipStream_t st);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 

@@ -1810,6 +1810,48 @@ hipError_t launch_finalize_grads(const SceneDev &s, int sh_k, float *acc, float 
   return hipGetLastError();
 }
 
+// Densification statistic of one view (Sec. 3.5, Eq. 12): the view's mean
+// gradient is -2 M^T dZ, dZ the change of the accumulated mean slots since the
+// previous view; densify[user i] += |mu - o| / f * |grad|, views += grad != 0.
+__global__ __launch_bounds__(256) void k_densify(int64_t n, const int32_t *__restrict__ counters,
+                                                 const uint32_t *__restrict__ perm,
+                                                 const float *__restrict__ geom,
+                                                 const float *__restrict__ acc,
+                                                 float *__restrict__ zprev, float ox, float oy,
+                                                 float oz, float inv_focal,
+                                                 float *__restrict__ densify,
+                                                 int32_t *__restrict__ views) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || i >= counters[0]) return;
+  const float *G = geom + (size_t)kGeomFloats * i;
+  float dz[3];
+  for (int r = 0; r < 3; r++) {
+    const float z = acc[(size_t)kAccFloats * i + r];
+    dz[r] = z - zprev[3 * i + r];
+    zprev[3 * i + r] = z;
+  }
+  float g2 = 0.0f;
+  for (int c = 0; c < 3; c++) {
+    const float gc = -2.0f * (G[G_M + c] * dz[0] + G[G_M + 3 + c] * dz[1] + G[G_M + 6 + c] * dz[2]);
+    g2 = fmaf(gc, gc, g2);
+  }
+  if (g2 > 0.0f) {
+    const float ex = G[G_MU] - ox, ey = G[G_MU + 1] - oy, ez = G[G_MU + 2] - oz;
+    const float alpha = sqrtf(ex * ex + ey * ey + ez * ez) * inv_focal;
+    const uint32_t u = perm[i];
+    densify[u] += alpha * sqrtf(g2);
+    views[u] += 1;
+  }
+}
+
+hipError_t launch_densify(const SceneDev &s, const float *acc, float *zprev, float ox, float oy,
+                          float oz, float focal, float *densify, int32_t *views, hipStream_t st) {
+  const unsigned nb = (unsigned)((s.n + 255) / 256);
+  k_densify<<<nb, 256, 0, st>>>(s.n, s.counters, s.perm, s.geom, acc, zprev, ox, oy, oz,
+                                1.0f / focal, densify, views);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(void *p, int64_t n_words, uint32_t value, hipStream_t st) {
   if (n_words <= 0) return hipSuccess;
   int64_t blocks = (n_words + 255) / 256;

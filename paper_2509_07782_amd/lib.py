@@ -51,7 +51,8 @@ class RenderOpts(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("density", C.c_void_p), ("sh", C.c_void_p), ("accumulate", C.c_int32)]
+                ("density", C.c_void_p), ("sh", C.c_void_p), ("accumulate", C.c_int32),
+                ("densify", C.c_void_p), ("densify_views", C.c_void_p)]
 
 
 EXPORTS = ("rgx_create", "rgx_destroy", "rgx_build_bvh", "rgx_bvh_destroy", "rgx_bvh_size",
@@ -252,12 +253,13 @@ def render_forward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, stats=Non
 
 
 def render_backward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, grad_rgb, grad_T, grads,
-                    accumulate=False, stream=0):
+                    accumulate=False, stream=0, densify=None, densify_views=None):
     arr = camera_array(cams)
     o = make_opts(opts)
     g = Grads(grads["means"].data_ptr(), grads["log_scales"].data_ptr(),
               grads["quats"].data_ptr(), grads["density"].data_ptr(), grads["sh"].data_ptr(),
-              int(bool(accumulate)))
+              int(bool(accumulate)), None if densify is None else densify.data_ptr(),
+              None if densify_views is None else densify_views.data_ptr())
     check(load().rgx_render_backward(ctx.h, bvh.h, arr, len(cams), C.byref(o), out_rgb.data_ptr(),
                                      out_T.data_ptr(), grad_rgb.data_ptr(),
                                      None if grad_T is None else grad_T.data_ptr(), C.byref(g),

@@ -74,11 +74,15 @@ class Renderer:
         lib.render_forward(self.ctx, self.bvh, cams, opts, rgb, T, st, _stream())
         return (rgb, T, st) if stats else (rgb, T)
 
-    def backward(self, cams, opts: RenderOptions, rgb, T, grad_rgb, grad_T, params: dict):
+    def backward(self, cams, opts: RenderOptions, rgb, T, grad_rgb, grad_T, params: dict,
+                 densify=None, densify_views=None):
+        """Parameter gradients; with `densify` / `densify_views` ([n] float32 /
+        int32 device tensors) also adds the densification statistic of each
+        view (per-view mean-gradient norms weighted by distance / focal)."""
         grads = {k: torch.empty_like(params[k]) for k in PARAM_KEYS}
         lib.render_backward(self.ctx, self.bvh, cams, opts, rgb, T, grad_rgb.contiguous(),
                             None if grad_T is None else grad_T.contiguous(), grads, False,
-                            _stream())
+                            _stream(), densify, densify_views)
         return grads
 
     def close(self):

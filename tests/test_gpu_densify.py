@@ -1,0 +1,77 @@
+"""Densification statistic (Sec. 3.5, Eq. 12) fused into the backward: for
+each view v, alpha_v |dL_v/dmu| with alpha_v = |mu - o_v| / f_v, summed over
+views, and the number of views with a non-zero mean gradient -- against the
+same quantities formed from the FP64 oracle's per-view adjoints."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_07782_amd import inputs
+from paper_2509_07782_amd.render import RenderOptions
+from helpers import PARAM_KEYS, grad_rel_errors, oracle_opts, renderer_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_densification_statistic_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    sc = inputs.make_scene("cluster", 2000, 11, sh_degree=3)
+    cams = [inputs.look_at_camera(41, 29, (0.0, 0.0, 3.0)),
+            inputs.look_at_camera(33, 37, (2.6, 0.4, 1.5)),
+            inputs.look_at_camera(45, 23, (-1.0, 2.5, -1.3))]
+    o = RenderOptions(dt=0.005, ess=1, t_eps=0.0)
+    r, params = renderer_for(sc)
+    rgb, T = r.forward(cams, o)
+    R = rgb.shape[0]
+    rng = np.random.default_rng(5)
+    gC = rng.normal(0.0, 1.0, (R, 3)).astype(np.float32)
+    gCt = torch.from_numpy(gC).cuda()
+    n = sc["means"].shape[0]
+    dens = torch.zeros(n, device="cuda")
+    views = torch.zeros(n, device="cuda", dtype=torch.int32)
+    g_dens = r.backward(cams, o, rgb, T, gCt, None, params, dens, views)
+    g_plain = r.backward(cams, o, rgb, T, gCt, None, params)
+    torch.cuda.synchronize()
+    # marching the views one at a time leaves the gradients unchanged (up to
+    # the order of FP32 atomics)
+    errs = grad_rel_errors({k: g_dens[k].cpu().numpy() for k in PARAM_KEYS},
+                           {k: g_plain[k].cpu().numpy() for k in PARAM_KEYS})
+    for k, (rel, frac) in errs.items():
+        assert rel <= 1e-5, (k, rel)
+    # oracle: per-view adjoints of the loss restricted to that view
+    ref = np.zeros(n)
+    ref_views = np.zeros(n, np.int64)
+    off = 0
+    mu = sc["means"].astype(np.float64)
+    for cam in cams:
+        m = cam.width * cam.height
+        g = oracle.backward(sc, cam, oracle_opts(o), np.arange(m), gC[off:off + m].astype(np.float64))
+        off += m
+        gn = np.linalg.norm(g["means"], axis=1)
+        c2w = np.asarray(cam.cam_to_world, np.float64).reshape(3, 4)
+        alpha = np.linalg.norm(mu - c2w[:, 3], axis=1) / float(cam.fx)
+        ref += alpha * gn
+        ref_views += gn > 0
+    d = dens.cpu().numpy().astype(np.float64)
+    v = views.cpu().numpy()
+    assert (ref_views > 0).mean() > 0.2
+    assert np.linalg.norm(d - ref) <= 1e-3 * np.linalg.norm(ref)
+    rms = np.sqrt(np.mean(ref * ref))
+    assert (np.abs(d - ref) <= 1e-3 * np.abs(ref) + 1e-3 * rms).mean() >= 0.999
+    # view counts: equal wherever the oracle gradient is not vanishingly small
+    clear = (ref == 0) | (ref > 1e-6 * ref.max())
+    assert (v[clear] == ref_views[clear]).mean() >= 0.999
+    # running sums: a second call adds the same amounts again
+    r.backward(cams, o, rgb, T, gCt, None, params, dens, views)
+    torch.cuda.synchronize()
+    assert np.allclose(dens.cpu().numpy(), 2 * d, rtol=1e-5, atol=1e-12)
+    assert np.array_equal(views.cpu().numpy(), 2 * v)
+    r.close()
