@@ -125,7 +125,9 @@ enum {
   RGX_STAT_SAMPLES,      /* samples evaluated (t < t_far, non-empty segments) */
   RGX_STAT_SEGMENTS,     /* non-empty segments processed */
   RGX_STAT_CLOSEST,      /* closest-hit queries */
-  RGX_STAT_BOX_ONLY,     /* leaves whose AABB met the segment but whose ellipsoid did not */
+  RGX_STAT_BOX_ONLY,     /* per ray, summed over its window collections: visited leaves whose
+                            AABB meets the ray's window interval while the ellipsoid chord
+                            does not (the AABB false positives) */
   RGX_STAT_NODES,        /* BVH nodes loaded by the wave for the segment collections */
   RGX_STAT_LEAVES,       /* leaves the wave visited for the segment collections */
   RGX_STAT_WINDOWS,      /* window collections the wave made (attempts included) */

@@ -9,6 +9,11 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   isotropic_loss     mean over Gaussians of max(r_max, r0) - r0 (Sec. 3.4, Eq. 8)
   adaptive_step      min(max(d/beta, dt_min) * T^(-1/3), dt_max) (Sec. 3.2, Eq. 5; the
                      segment is N_S times this)
+  densification_statistic
+                     per Gaussian: sum over views of alpha_v |grad_mu L_v| with
+                     alpha_v = |mu - o_v| / f_v, and the number of views whose gradient
+                     is non-zero (Sec. 3.5, Eq. 12; the ratio of the two is the average
+                     the criterion thresholds)
 """
 from __future__ import annotations
 
@@ -40,3 +45,21 @@ def adaptive_step(d, T, dt_min=0.005, dt_max=0.02, beta=1024.0):
     with np.errstate(divide="ignore"):
         v = np.maximum(d / beta, dt_min) * T ** (-1.0 / 3.0)
     return np.minimum(v, dt_max)
+
+
+def densification_statistic(means, grads_mu, origins, focals):
+    """means [N,3]; grads_mu [V,N,3] the per-view gradients of the loss with
+    respect to the means; origins [V,3] camera centres; focals [V] focal
+    lengths in pixels.  Returns (sum [N], views [N])."""
+    mu = np.asarray(means, np.float64)
+    g = np.asarray(grads_mu, np.float64)
+    o = np.asarray(origins, np.float64)
+    f = np.asarray(focals, np.float64)
+    total = np.zeros(mu.shape[0])
+    views = np.zeros(mu.shape[0], np.int64)
+    for v in range(g.shape[0]):
+        gn = np.linalg.norm(g[v], axis=1)
+        alpha = np.linalg.norm(mu - o[v], axis=1) / f[v]
+        total += alpha * gn
+        views += gn > 0
+    return total, views

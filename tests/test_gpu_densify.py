@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import geometry
 from paper_2509_07782_amd import inputs
 from paper_2509_07782_amd.render import RenderOptions
 from helpers import PARAM_KEYS, grad_rel_errors, oracle_opts, renderer_for
@@ -46,20 +47,17 @@ def test_densification_statistic_matches_oracle(torch_cuda):
                            {k: g_plain[k].cpu().numpy() for k in PARAM_KEYS})
     for k, (rel, frac) in errs.items():
         assert rel <= 1e-5, (k, rel)
-    # oracle: per-view adjoints of the loss restricted to that view
-    ref = np.zeros(n)
-    ref_views = np.zeros(n, np.int64)
+    # oracle: per-view adjoints of the loss restricted to that view, then Eq. 12
+    gmu, origins, focals = [], [], []
     off = 0
-    mu = sc["means"].astype(np.float64)
     for cam in cams:
         m = cam.width * cam.height
         g = oracle.backward(sc, cam, oracle_opts(o), np.arange(m), gC[off:off + m].astype(np.float64))
         off += m
-        gn = np.linalg.norm(g["means"], axis=1)
-        c2w = np.asarray(cam.cam_to_world, np.float64).reshape(3, 4)
-        alpha = np.linalg.norm(mu - c2w[:, 3], axis=1) / float(cam.fx)
-        ref += alpha * gn
-        ref_views += gn > 0
+        gmu.append(g["means"])
+        origins.append(np.asarray(cam.cam_to_world, np.float64).reshape(3, 4)[:, 3])
+        focals.append(float(cam.fx))
+    ref, ref_views = geometry.densification_statistic(sc["means"], np.stack(gmu), origins, focals)
     d = dens.cpu().numpy().astype(np.float64)
     v = views.cpu().numpy()
     assert (ref_views > 0).mean() > 0.2

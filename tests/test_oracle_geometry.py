@@ -219,3 +219,47 @@ def test_rays_reproject_to_pixel_centres():
     np.testing.assert_allclose(u, pix % 37 + 0.5, atol=1e-4)
     np.testing.assert_allclose(v, pix // 37 + 0.5, atol=1e-4)
     assert np.all(xc[:, 2] > 0)
+
+
+def test_densification_weight_is_projected_gradient():
+    """Supp. (densification criterion and the projected mean): for a loss that
+    depends on mu only through its projection mu_P = o + f (mu - o)/|mu - o|
+    onto the sphere of radius f about the camera, the gradient along that
+    sphere has norm (r/f)|grad_mu L|, r = |mu - o|.  The oracle's per-view
+    weight alpha |grad_mu L| must equal that norm (autograd, FP64)."""
+    import torch
+    rng = np.random.default_rng(3)
+    V, N = 3, 64
+    o = rng.normal(0.0, 2.0, (V, 3))
+    f = rng.uniform(300.0, 1500.0, V)
+    mu = rng.normal(0.0, 3.0, (N, 3))
+    w = torch.tensor(rng.normal(0.0, 1.0, (N, 3)), dtype=torch.float64)
+    grads, proj_norms = [], []
+    for v in range(V):
+        ov = torch.tensor(o[v])
+
+        def h(p):   # any smooth function of the projected point
+            q = (p - ov) / f[v]
+            return (torch.sin(q * w) * q.roll(1, dims=1)).sum() + (q[:, 0] * q[:, 2] ** 2).sum()
+
+        m = torch.tensor(mu, requires_grad=True)
+        d = m - ov
+        P = ov + f[v] * d / d.norm(dim=1, keepdim=True)
+        h(P).backward()
+        grads.append(m.grad.numpy().copy())
+        p = P.detach().clone().requires_grad_(True)
+        h(p).backward()
+        u = (d / d.norm(dim=1, keepdim=True)).detach()
+        gp = p.grad - (p.grad * u).sum(dim=1, keepdim=True) * u     # tangential part
+        proj_norms.append(gp.norm(dim=1).numpy())
+        # the assumption of the derivation holds here: no radial component
+        assert np.abs((m.grad * u).sum(dim=1).numpy()).max() <= 1e-12 * m.grad.norm().item() + 1e-300
+    tot, views = geometry.densification_statistic(mu, np.stack(grads), o, f)
+    assert np.allclose(tot, np.sum(proj_norms, axis=0), rtol=1e-12, atol=0.0)
+    assert np.array_equal(views, np.full(N, V))
+    # a view in which a Gaussian gets no gradient adds nothing and is not counted
+    g0 = np.stack(grads)
+    g0[1, :10] = 0.0
+    tot0, views0 = geometry.densification_statistic(mu, g0, o, f)
+    assert np.array_equal(views0[:10], np.full(10, V - 1))
+    assert np.allclose(tot0[:10], proj_norms[0][:10] + proj_norms[2][:10], rtol=1e-12)
