@@ -132,21 +132,27 @@ __device__ __forceinline__ Chord chord(const Gauss &g, const Ray &r) {
   return c;
 }
 
-// Colour of a Gaussian at the lane's direction: c = sum_m f_m Y_m.
+// Colour of a Gaussian at the lane's direction: c = sum_m f_m Y_m.  The
+// record's float4s are read without branches: past the record's end the
+// index is clamped to its last float4, whose entries (and every entry past
+// 3 sh_k, zero padding) meet Y_m = 0 for m >= sh_k, so the extra terms add
+// exact zeros and all twelve scalar loads issue before the first use.
 __device__ __forceinline__ void colour(const float *col, int j, int col_stride, int sh_k,
                                        const float *Y, float &cr, float &cg, float &cb) {
+  (void)sh_k;
   cfloat4p p = as_const4(col) + (size_t)(col_stride >> 2) * j;
+  const int last = (col_stride >> 2) - 1;
+  vf4 f[12];
+#pragma unroll
+  for (int q = 0; q < 12; q++) f[q] = p[q < last ? q : last];
   float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int q = 0; q < 12; q++) {
-    if (4 * q < 3 * sh_k) {
-      const vf4 f = p[q];
-      const float fv[4] = {f.x, f.y, f.z, f.w};
+    const float fv[4] = {f[q].x, f[q].y, f[q].z, f[q].w};
 #pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const int flat = 4 * q + e;
-        if (flat < 3 * sh_k) acc[flat % 3] = fmaf(fv[e], Y[flat / 3], acc[flat % 3]);
-      }
+    for (int e = 0; e < 4; e++) {
+      const int flat = 4 * q + e;
+      acc[flat % 3] = fmaf(fv[e], Y[flat / 3], acc[flat % 3]);
     }
   }
   cr = acc[0]; cg = acc[1]; cb = acc[2];
@@ -1539,9 +1545,11 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
                     dummy_nodes, dummy_leaves, dummy_windows, go);
       const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
       const float lo = go ? a : kInf, hi = go ? b : -kInf;
-      float sg[NS], W0[NS], W1[NS], W2[NS];
+      // only G . W_k enters the adjoints, so pass A sums the Gaussians'
+      // weights times G . c_l, one scalar per sample
+      float sg[NS], GW[NS];
 #pragma unroll
-      for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
+      for (int k = 0; k < NS; k++) { sg[k] = 0.0f; GW[k] = 0.0f; }
       int nhit = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
@@ -1556,20 +1564,20 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
           nhit++;
           float cr, cg, cb;
           colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
+          const float gc = fmaf(Gc0, cr, fmaf(Gc1, cg, Gc2 * cb));
           float wk[NS];
           sample_weights<NS>(g, c, sp, wk);
 #pragma unroll
           for (int k = 0; k < NS; k++) {
             sg[k] += wk[k];
-            W0[k] = fmaf(wk[k], cr, W0[k]);
-            W1[k] = fmaf(wk[k], cg, W1[k]);
-            W2[k] = fmaf(wk[k], cb, W2[k]);
+            GW[k] = fmaf(wk[k], gc, GW[k]);
           }
         }
       }); while (next_chunk(s, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
                             dummy_nodes, dummy_leaves, dummy_windows));
 
-      // per-sample adjoints: dL/dsigma_k (into sg) and dL/dW_k (into W)
+      // per-sample adjoints: dL/dsigma_k (into sg) and T_k phi_k (into GW);
+      // dL/dW_k is G T_k phi_k
       const bool any = go && nhit > 0;
       if (any) {
 #pragma unroll
@@ -1585,16 +1593,13 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
             const float dphi = x < 1e-2f
                 ? dt * dt * (-0.5f + x * (1.0f / 3.0f - x * (0.125f - x * (1.0f / 30.0f))))
                 : (x * E - alpha) * rs * rs;
-            const float GW = Gc0 * W0[k] + Gc1 * W1[k] + Gc2 * W2[k];
-            GP = fmaf(T * phi, GW, GP);
-            dsig = T * dphi * GW - dt * (GCf - GP);
+            GP = fmaf(T * phi, GW[k], GP);
+            dsig = T * dphi * GW[k] - dt * (GCf - GP);
             dW = T * phi;
             T *= E;
           }
           sg[k] = dsig;
-          W0[k] = dW * Gc0;
-          W1[k] = dW * Gc1;
-          W2[k] = dW * Gc2;
+          GW[k] = dW;
         }
       }
 
@@ -1608,29 +1613,31 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
           const Chord c = chord(g, r);
           const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
           if (ballot(hit) == 0) return;
-          float D0 = 0.0f, D1 = 0.0f, D2 = 0.0f, dc0 = 0.0f, dc1 = 0.0f, dc2 = 0.0f, ds = 0.0f;
+          float dc0 = 0.0f, dc1 = 0.0f, dc2 = 0.0f;
           float v[16];
 #pragma unroll
           for (int e2 = 0; e2 < 16; e2++) v[e2] = 0.0f;
           if (hit) {
             float cr, cg, cb;
             colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
+            const float gc = fmaf(Gc0, cr, fmaf(Gc1, cg, Gc2 * cb));
             float wk[NS];
             sample_weights<NS>(g, c, sp, wk);
+            // dL/dw_k = dsigma_k + G.c_l T_k phi_k; dq_k = -w_k dL/dw_k / 2
+            float ds = 0.0f, E1 = 0.0f, E2 = 0.0f, S = 0.0f;
 #pragma unroll
             for (int k = 0; k < NS; k++) {
               const float u = fmaf((float)k, sp.dt, sp.t0 - c.ts);
-              const float dw = sg[k] + W0[k] * cr + W1[k] * cg + W2[k] * cb;
-              const float wdw = wk[k] * dw;
+              const float wdw = wk[k] * fmaf(GW[k], gc, sg[k]);
               ds += wdw;
-              const float dq = -0.5f * wdw;
-              D0 += dq;
-              D1 = fmaf(dq, u, D1);
-              D2 = fmaf(dq * u, u, D2);
-              dc0 = fmaf(wk[k], W0[k], dc0);
-              dc1 = fmaf(wk[k], W1[k], dc1);
-              dc2 = fmaf(wk[k], W2[k], dc2);
+              E1 = fmaf(wdw, u, E1);
+              E2 = fmaf(wdw * u, u, E2);
+              S = fmaf(wk[k], GW[k], S);
             }
+            const float D0 = -0.5f * ds, D1 = -0.5f * E1, D2 = -0.5f * E2;
+            dc0 = S * Gc0;
+            dc1 = S * Gc1;
+            dc2 = S * Gc2;
             // z_k = p + u_k d' with p = o' + t* d' (closest approach, local frame)
             const float pxl = fmaf(c.ts, dpx, opx), pyl = fmaf(c.ts, dpy, opy),
                         pzl = fmaf(c.ts, dpz, opz);
