@@ -197,7 +197,7 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   }
   const int64_t n = g->n;
   const int sh_k = (g->sh_degree + 1) * (g->sh_degree + 1);
-  const int col_stride = (3 * sh_k + 3) & ~3;
+  const int col_stride = kColFloats;   // fixed record length: the march reads it unconditionally
   const int64_t nb = (n + 4095) / 4096;
   const size_t nodes_n = (size_t)std::max<int64_t>(n - 1, 1);
   hipError_t e = hipSuccess;

@@ -11,6 +11,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxViewsPerLaunch = 24;    // view table travels as a kernel argument
 constexpr int kGeomFloats = 16;           // packed geometry record (64 B)
 constexpr int kAccFloats = 64;            // per-Gaussian gradient accumulator (256 B)
+constexpr int kColFloats = 48;            // colour record: 3 x 16 SH coefficients, zero past the degree
 // 4-wide node record: 4 child boxes (lo xyz, hi xyz), 4 child links (>= 0
 // 4-wide node, < 0 leaf ~j, kNoChild none), 4 leaf ranges (first, last).
 constexpr int kNode4Floats = 36;

@@ -132,22 +132,19 @@ __device__ __forceinline__ Chord chord(const Gauss &g, const Ray &r) {
   return c;
 }
 
-// Colour of a Gaussian at the lane's direction: c = sum_m f_m Y_m.  The
-// record's float4s are read without branches: past the record's end the
-// index is clamped to its last float4, whose entries (and every entry past
-// 3 sh_k, zero padding) meet Y_m = 0 for m >= sh_k, so the extra terms add
-// exact zeros and all twelve scalar loads issue before the first use.
-__device__ __forceinline__ void colour(const float *col, int j, int col_stride, int sh_k,
-                                       const float *Y, float &cr, float &cg, float &cb) {
-  (void)sh_k;
-  cfloat4p p = as_const4(col) + (size_t)(col_stride >> 2) * j;
-  const int last = (col_stride >> 2) - 1;
-  vf4 f[12];
+// Colour of a Gaussian at the lane's direction: c = sum_m f_m Y_m.  Every
+// colour record is kColFloats long whatever the degree (zero past 3 sh_k) and
+// Y_m = 0 for m >= sh_k, so the record is read at fixed offsets, without
+// branches, and the terms past the degree add exact zeros.
+__device__ __forceinline__ void colour(const float *col, int j, const float *Y, float &cr,
+                                       float &cg, float &cb) {
+  cfloat4p p = as_const4(col) + (size_t)(kColFloats / 4) * j;
+  vf4 f[kColFloats / 4];
 #pragma unroll
-  for (int q = 0; q < 12; q++) f[q] = p[q < last ? q : last];
+  for (int q = 0; q < kColFloats / 4; q++) f[q] = p[q];
   float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int q = 0; q < 12; q++) {
+  for (int q = 0; q < kColFloats / 4; q++) {
     const float fv[4] = {f[q].x, f[q].y, f[q].z, f[q].w};
 #pragma unroll
     for (int e = 0; e < 4; e++) {
@@ -1377,7 +1374,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
             n_dump++;
           }
           float cr, cg, cb;
-          colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
+          colour(s.col, j, Y, cr, cg, cb);
           float wk[NS];
           sample_weights<NS>(g, c, sp, wk);
 #pragma unroll
@@ -1563,7 +1560,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         if (hit) {
           nhit++;
           float cr, cg, cb;
-          colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
+          colour(s.col, j, Y, cr, cg, cb);
           const float gc = fmaf(Gc0, cr, fmaf(Gc1, cg, Gc2 * cb));
           float wk[NS];
           sample_weights<NS>(g, c, sp, wk);
@@ -1619,7 +1616,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
           for (int e2 = 0; e2 < 16; e2++) v[e2] = 0.0f;
           if (hit) {
             float cr, cg, cb;
-            colour(s.col, j, op.col_stride, op.sh_k, Y, cr, cg, cb);
+            colour(s.col, j, Y, cr, cg, cb);
             const float gc = fmaf(Gc0, cr, fmaf(Gc1, cg, Gc2 * cb));
             float wk[NS];
             sample_weights<NS>(g, c, sp, wk);
