@@ -1110,33 +1110,51 @@ __device__ __forceinline__ Gauss gauss_from_lane(const Gauss &v, int src) {
   return g;
 }
 
+// Entries of M.order carry a mark bit above the slot index: set by a MARK
+// pass for the entries some lane hit, read by a FILTER pass over the same
+// list and the same segments.
+constexpr int kOrderMark = 1 << 16;
+enum CandMode { CAND_ALL = 0, CAND_MARK = 1, CAND_FILTER = 2 };
+
 // Calls fn(j, g) for every candidate j with its geometry record g.
 // `a_min`/`b_max` bound the live lanes' segments for the list's uniform
 // depth pre-check.  List entries are taken 64 at a time: lane i holds entry
 // base + i and loads that entry's geometry, so one memory round trip serves
 // the whole block; the surviving candidates are then read back with readlane.
-template <class Fn>
-__device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, const WaveMem &M,
+// CAND_MARK: fn returns whether some lane hit the candidate, and the entry's
+// mark is set to that; CAND_FILTER: only marked entries are visited (list
+// source only; the brute-force source visits everything).
+template <int MODE = CAND_ALL, class Fn>
+__device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, WaveMem &M,
                                                    int count, int lane, float a_min, float b_max,
                                                    int n_active, const Ray &r, Fn &&fn) {
   const float ox = r.ox, oy = r.oy, oz = r.oz;
   if (kind == SRC_LIST) {
     for (int base = 0; base < count; base += 64) {
       const int e = base + lane;
-      int id = 0;
+      int id = 0, o = 0;
       bool keep = false;
       if (e < count) {
-        const int o = M.order[e];
+        const int om = M.order[e];
+        o = om & (kOrderMark - 1);
         keep = !(M.l_tin[o] > b_max) && !(M.l_tout[o] < a_min);
+        if (MODE == CAND_FILTER) keep = keep && (om & kOrderMark) != 0;
         id = M.l_id[o];
       }
       const uint64_t bits0 = ballot(keep);
       if (!bits0) continue;
       const Gauss mine = with_origin(load_gauss_lane(s.geom, keep ? id : 0), ox, oy, oz);
+      bool hit_mine = false;
       for (uint64_t bits = bits0; bits; bits &= bits - 1) {
         const int src = __builtin_ctzll(bits);
-        fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src));
+        if constexpr (MODE == CAND_MARK) {
+          const bool h = fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src));
+          hit_mine = lane == src ? h : hit_mine;
+        } else {
+          fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src));
+        }
       }
+      if (MODE == CAND_MARK && keep) M.order[e] = o | (hit_mine ? kOrderMark : 0);
     }
   } else {
     for (int e = 0; e < n_active; e++) fn(e, with_origin(load_gauss(s.geom, e), ox, oy, oz));
@@ -1550,13 +1568,13 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       int nhit = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
-      do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
-                            [&](int j, const Gauss &g) {
+      do for_each_candidate<CAND_MARK>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
+                                       [&](int j, const Gauss &g) {
         const bool want = go;
-        if (ballot(want) == 0) return;
+        if (ballot(want) == 0) return false;
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
-        if (ballot(hit) == 0) return;
+        if (ballot(hit) == 0) return false;
         if (hit) {
           nhit++;
           float cr, cg, cb;
@@ -1570,6 +1588,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
             GW[k] = fmaf(wk[k], gc, GW[k]);
           }
         }
+        return true;
       }); while (next_chunk(s, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
                             dummy_nodes, dummy_leaves, dummy_windows));
 
@@ -1663,8 +1682,10 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         };
         // the list still holds the whole window, or the segment's last Z
         // chunk [zlast, end); a chunked segment then collects [0, zlast) again
+        // (pass A marked the entries of that list some lane hit)
         const int zlast = win.chunked ? win.t.z0 : 0;
-        for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, pass_b);
+        for_each_candidate<CAND_FILTER>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
+                                        pass_b);
         if (win.chunked && zlast > 0) {
           first_chunk(s, M, r, lane, n_active, any, a, b, zlast, win, false, ls.error_flag,
                       dummy_nodes, dummy_leaves, dummy_windows);
