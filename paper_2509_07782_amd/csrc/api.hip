@@ -423,12 +423,13 @@ static rgx_status view_tables(rgx_context *ctx, const rgx_camera *cams, int n_vi
   return RGX_OK;
 }
 
-static LaunchShape shape_for(rgx_context *ctx, const MarchOpts &m, int n_tiles) {
+// waves_per_cu: how many of the kernel's one-wave workgroups fit on a CU
+static LaunchShape shape_for(rgx_context *ctx, const MarchOpts &m, int n_tiles, int waves_per_cu) {
   LaunchShape ls;
   ls.queue = ctx->queue;
   ls.error_flag = ctx->queue + 8;
   // one wave (one 64-ray tile) per workgroup
-  ls.grid = m.persistent ? std::min(n_tiles, ctx->n_cu * 12) : n_tiles;
+  ls.grid = m.persistent ? std::min(n_tiles, ctx->n_cu * waves_per_cu) : n_tiles;
   if (ls.grid < 1) ls.grid = 1;
   return ls;
 }
@@ -454,7 +455,7 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
   for (const ViewTable &t : tabs) {
     if (t.n_tiles == 0) continue;
     HIP_TRY(ctx, timed(ctx, RGX_KERN_FORWARD, stream,
-                       [&] { return launch_forward(sd, t, m, out, shape_for(ctx, m, t.n_tiles), stream); }));
+                       [&] { return launch_forward(sd, t, m, out, shape_for(ctx, m, t.n_tiles, fwd_waves_per_cu(m)), stream); }));
   }
   return RGX_OK;
 }
@@ -485,7 +486,7 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
     for (const ViewTable &t : tabs) {
       if (t.n_tiles == 0) continue;
       HIP_TRY(ctx, timed(ctx, RGX_KERN_BACKWARD, stream,
-                         [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles), stream); }));
+                         [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles, bwd_waves_per_cu(m)), stream); }));
     }
   } else {
     // one view at a time: each view's mean gradient is the change of the
@@ -502,7 +503,7 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
       for (const ViewTable &t : one) {
         if (t.n_tiles == 0) continue;
         HIP_TRY(ctx, timed(ctx, RGX_KERN_BACKWARD, stream,
-                           [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles), stream); }));
+                           [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles, bwd_waves_per_cu(m)), stream); }));
       }
       const float *c2w = cams[v].cam_to_world;
       HIP_TRY(ctx, launch_densify(sd, (const float *)bvh->acc.p, (float *)mb->zprev.p, c2w[3], c2w[7],
@@ -545,7 +546,7 @@ rgx_status rgx_dump_hits(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera 
   out.dump_a = seg_a;
   out.dump_ids = ids;
   out.dump_count = count;
-  HIP_TRY(ctx, launch_forward(scene_of(bvh), t, m, out, shape_for(ctx, m, t.n_tiles), stream));
+  HIP_TRY(ctx, launch_forward(scene_of(bvh), t, m, out, shape_for(ctx, m, t.n_tiles, fwd_waves_per_cu(m)), stream));
   return RGX_OK;
 }
 

@@ -65,6 +65,10 @@ struct LaunchShape {
   int32_t *error_flag;
 };
 
+// Resident one-wave workgroups per CU of the march kernels (their launch
+// bounds and LDS use), used to size persistent grids.
+inline int fwd_waves_per_cu(const MarchOpts &m) { return m.n_s <= 8 ? 12 : 8; }
+inline int bwd_waves_per_cu(const MarchOpts &) { return 8; }
 hipError_t launch_forward(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
                           const FwdOut &out, const LaunchShape &ls, hipStream_t st);
 hipError_t launch_backward(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,

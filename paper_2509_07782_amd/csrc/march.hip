@@ -351,23 +351,85 @@ __device__ __forceinline__ void dpp_stage(float *x, int lane) {
   }
 }
 
-// Reduce-scatter over the wave of the 64 gradient slots of one Gaussian:
-// slots [0,16) are g[0..15]; slot 16 + 16 ch + m is Y[m] * dc[ch] (SH
-// coefficient m of channel ch).  Returns, in lane L, the wave total of slot L.
-// Slot index i and its partners i+16, i+32, i+48 meet in x[i] after one
-// permlane32 and one permlane16 exchange; four in-row DPP stages (mirror,
-// half mirror, quad xor 2, quad xor 1) then split the 16 rows' values.
-__device__ __forceinline__ float wave_reduce_slots(const float *g, const float *Y, float dc0,
-                                                   float dc1, float dc2, int lane) {
-  float x[16];
-#pragma unroll
-  for (int i = 0; i < 16; i++)
-    x[i] = swap16_sum(swap32_sum(g[i], Y[i] * dc1), swap32_sum(Y[i] * dc0, Y[i] * dc2));
+// Sum over the wave of 16 per-lane slots: the in-row DPP stages leave lane
+// p of each row the row's total of slot p, two half-wave swaps add the rows.
+// Lane L returns the wave total of slot L & 15.
+__device__ __forceinline__ float wave_sum_slots16(float *x, int lane) {
   dpp_stage<8, 0x140>(x, lane);   // row_mirror: lane p <-> 15 - p
   dpp_stage<4, 0x141>(x, lane);   // row_half_mirror: p <-> 7 - p within 8
   dpp_stage<2, 0x4e>(x, lane);    // quad_perm [2,3,0,1]
   dpp_stage<1, 0xb1>(x, lane);    // quad_perm [1,0,3,2]
-  return x[0];
+  const float y = swap32_sum(x[0], x[0]);
+  return swap16_sum(y, y);
+}
+
+// SH-coefficient gradients of a batch of up to 16 Gaussians as a matrix
+// product on the matrix cores.  For Gaussian b of the batch and channel c,
+// dL/df_{m,c} = sum over the tile's rays r of Y_m(d_r) G_c(r) S_b(r), S_b(r)
+// the ray's sum over samples of w_k dL/dW_k-weight (zero where the ray misses
+// b).  With A_c[m][r] = Y_m(d_r) G_c(r) fixed for the tile and B[r][b] =
+// S_b(r) staged in LDS, each channel is 16 chained 16x16x4 FP32 MFMAs over the
+// 64 rays.  Operand layout of v_mfma_f32_16x16x4_f32 (wave64): A[i][k] in lane
+// i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i / 4), register
+// i % 4.
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kSbStride = 66;   // floats per staged row: transposed reads hit distinct banks
+
+struct ShBatch {
+  float a[3][16];   // A_c for rays 4s + (lane >> 4), row m = lane & 15
+  int n = 0;        // uniform: staged Gaussians
+  int id = 0;       // lane b < 16: the Gaussian staged in row b
+};
+
+// A_c of a new tile; `tmp` is 192 floats of LDS free at that point.
+__device__ __forceinline__ void sh_batch_start(ShBatch &B, float *sb, float *tmp, const float *Y,
+                                               float g0, float g1, float g2, int lane) {
+#pragma unroll
+  for (int m = 0; m < 16; m++) sb[m * kSbStride + lane] = Y[m];
+  tmp[lane] = g0;
+  tmp[64 + lane] = g1;
+  tmp[128 + lane] = g2;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    const int ray = 4 * q + (lane >> 4);
+    const float y = sb[(lane & 15) * kSbStride + ray];
+    B.a[0][q] = y * tmp[ray];
+    B.a[1][q] = y * tmp[64 + ray];
+    B.a[2][q] = y * tmp[128 + ray];
+  }
+  __builtin_amdgcn_wave_barrier();
+  B.n = 0;
+}
+
+// Multiplies out the staged batch and adds it to the accumulators.
+__device__ __forceinline__ void sh_batch_flush(ShBatch &B, const float *sb, float *acc, int sh_k,
+                                               int lane) {
+  if (B.n == 0) return;
+  __builtin_amdgcn_wave_barrier();
+  f4v d0 = {0.0f, 0.0f, 0.0f, 0.0f}, d1 = d0, d2 = d0;
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    const float bv = sb[(lane & 15) * kSbStride + 4 * q + (lane >> 4)];
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[0][q], bv, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[1][q], bv, d1, 0, 0, 0);
+    d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[2][q], bv, d2, 0, 0, 0);
+  }
+  const int jb = __shfl(B.id, lane & 15, 64);
+  if ((lane & 15) < B.n) {
+    float *row = acc + (size_t)kAccFloats * jb + 16;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int m = 4 * (lane >> 4) + i;
+      if (m < sh_k) {
+        unsafeAtomicAdd(row + m, d0[i]);
+        unsafeAtomicAdd(row + 16 + m, d1[i]);
+        unsafeAtomicAdd(row + 32 + m, d2[i]);
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  B.n = 0;
 }
 
 __device__ __forceinline__ float wave_sum_f(float v) {
@@ -1474,13 +1536,19 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
 // Backward kernel: replays the forward's segments from the same window lists
 // (or brute force / depth-first sources) in the same order, recomputes the
 // transmittance before every sample, derives dL/dsigma_k and dL/dW_k, then
-// revisits the segment's Gaussians for their parameter adjoints, reduced over
-// the wave before one atomic per accumulator slot.
+// revisits the Gaussians some lane hit for their parameter adjoints.  The 16
+// geometry and density slots are summed over the wave (DPP and half-wave
+// swaps) before one atomic per slot; the SH-coefficient slots, a per-ray
+// constant times one scalar per (ray, Gaussian), are staged 16 Gaussians at a
+// time and multiplied out on the matrix cores.  Two waves per SIMD: the
+// tile's matrix operand and the staging buffer need the registers and LDS.
 
 template <int NS>
-__global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s, ViewTable vt, MarchOpts op,
+__global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt, MarchOpts op,
                                                     BwdIn in, LaunchShape ls) {
   __shared__ WaveMem M;
+  __shared__ float sb[16 * kSbStride];   // staged S rows of the SH batch
+  ShBatch shb;
   const int lane = threadIdx.x;
   const int n_active = uniform_int(s.counters[0]);
   const bool grid = !op.adaptive && op.ess != 2;
@@ -1516,6 +1584,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       // C_fin - (prefix through k), kept as the running scalar GP = G . prefix
       GCf = Gc0 * in.rgb[q] + Gc1 * in.rgb[q + 1] + Gc2 * in.rgb[q + 2] + gT * in.T[px.ray];
     }
+    // (the list arrays are free before the tile's first window)
+    sh_batch_start(shb, sb, M.l_tin, Y, Gc0, Gc1, Gc2, lane);
     float GP = 0.0f;
     SegState ss;
     ss.alive = px.valid;
@@ -1619,7 +1689,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
         }
       }
 
-      // pass B: per-Gaussian adjoints, wave-reduced, one atomic per slot
+      // pass B: per-Gaussian adjoints
       if (ballot(any) != 0) {
         auto pass_b = [&](int j, const Gauss &g) {
           const bool want = any;
@@ -1629,7 +1699,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
           const Chord c = chord(g, r);
           const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
           if (ballot(hit) == 0) return;
-          float dc0 = 0.0f, dc1 = 0.0f, dc2 = 0.0f;
+          float S = 0.0f;
           float v[16];
 #pragma unroll
           for (int e2 = 0; e2 < 16; e2++) v[e2] = 0.0f;
@@ -1640,7 +1710,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
             float wk[NS];
             sample_weights<NS>(g, c, sp, wk);
             // dL/dw_k = dsigma_k + G.c_l T_k phi_k; dq_k = -w_k dL/dw_k / 2
-            float ds = 0.0f, E1 = 0.0f, E2 = 0.0f, S = 0.0f;
+            float ds = 0.0f, E1 = 0.0f, E2 = 0.0f;
 #pragma unroll
             for (int k = 0; k < NS; k++) {
               const float u = fmaf((float)k, sp.dt, sp.t0 - c.ts);
@@ -1651,9 +1721,6 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
               S = fmaf(wk[k], GW[k], S);
             }
             const float D0 = -0.5f * ds, D1 = -0.5f * E1, D2 = -0.5f * E2;
-            dc0 = S * Gc0;
-            dc1 = S * Gc1;
-            dc2 = S * Gc2;
             // z_k = p + u_k d' with p = o' + t* d' (closest approach, local frame)
             const float pxl = fmaf(c.ts, dpx, opx), pyl = fmaf(c.ts, dpy, opy),
                         pzl = fmaf(c.ts, dpz, opz);
@@ -1675,10 +1742,13 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
             v[14] = fmaf(D0, pzl * pzl, fmaf(2.0f * D1, pzl * dpz, D2 * dpz * dpz));
             v[15] = ds * __builtin_amdgcn_rcpf(g.sig);
           }
-          // slots: [0,16) geometry and density, then 16 SH coefficients per channel
-          const float mine = wave_reduce_slots(v, Y, dc0, dc1, dc2, lane);
-          if (lane < 16 || (lane & 15) < op.sh_k)
-            unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + lane, mine);
+          // slots [0,16): geometry and density, summed over the wave; the SH
+          // slots go through the matrix-core batch
+          sb[shb.n * kSbStride + lane] = S;
+          shb.id = lane == shb.n ? j : shb.id;
+          const float mine = wave_sum_slots16(v, lane);
+          if (lane < 16) unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + lane, mine);
+          if (++shb.n == 16) sh_batch_flush(shb, sb, in.acc, op.sh_k, lane);
         };
         // the list still holds the whole window, or the segment's last Z
         // chunk [zlast, end); a chunked segment then collects [0, zlast) again
@@ -1711,6 +1781,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_backward(SceneDev s,
       }
       if (go) step_after(op, grid, nhit > 0, best, tn, dS, b, ss);
     }
+    sh_batch_flush(shb, sb, in.acc, op.sh_k, lane);
   }
 }
 

@@ -62,6 +62,28 @@ def test_backward_matches_oracle(small_setup, torch_cuda, mode):
         assert frac >= 0.999, (k, frac)
 
 
+@pytest.mark.parametrize("deg,ns", [(0, 2), (1, 16), (2, 1), (3, 4)])
+def test_backward_sh_degrees_and_segment_sizes(torch_cuda, deg, ns):
+    """Every SH degree (the SH-coefficient gradients go through the per-tile
+    matrix product, masked past the degree) and segment sizes other than 8,
+    against the oracle adjoint."""
+    sc = inputs.make_scene("cluster", 2500, 41 + deg, sh_degree=deg)
+    cam = inputs.look_at_camera(29, 23, (0.2, 0.3, 2.7), fov_deg=42.0)
+    r, params = renderer_for(sc)
+    rng = np.random.default_rng(9)
+    n = cam.width * cam.height
+    gC = rng.standard_normal((n, 3)).astype(np.float32)
+    o = _opts(dt=0.005, ess=1, t_eps=1e-4, n_s=ns)
+    g = _gpu_grads(torch_cuda, r, cam, o, params, gC, None)
+    ref = oracle.backward(sc, cam, oracle_opts(o), np.arange(n), gC.astype(np.float64))
+    assert np.size(g["sh"]) == ref["sh"].size == sc["means"].shape[0] * (deg + 1) ** 2 * 3
+    errs = grad_rel_errors(g, ref)
+    for k, (rel, frac) in errs.items():
+        assert rel <= 1e-3, (deg, ns, k, rel)
+        assert frac >= 0.999, (deg, ns, k, frac)
+    r.close()
+
+
 def test_backward_bvh_equals_brute_force(small_setup, torch_cuda):
     sc, cam, r, params, gC, gT = small_setup
     a = _gpu_grads(torch_cuda, r, cam, _opts(dt=0.005, brute_force=True), params, gC, gT)
