@@ -167,7 +167,11 @@ int64_t rgx_bvh_size(const rgx_bvh *bvh);
 
 /* Forward render of n_views views (host array) through Algorithm 1.
    out_rgb [R,3] and out_T [R] with R = sum of width*height; `stats`
-   (nullable) receives [R, RGX_NSTAT] int32 counters. */
+   (nullable) receives [R, RGX_NSTAT] int32 counters.  With empty-space
+   skipping on, the forward also records each ray's first four closest-hit
+   results (Alg. 1 ClosestHit, Eq. 4) in a context-owned buffer (16 B per
+   ray, grown on demand; outgrown buffers are kept until rgx_destroy), keyed
+   by the structure, its build, the cameras and the options. */
 rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
                               int32_t n_views, const rgx_render_opts *opts, float *out_rgb,
                               float *out_T, int32_t *stats, hipStream_t stream);
@@ -178,7 +182,11 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
    restarts and the truncation boundaries are treated as constants.  The
    segments are re-traversed in the forward's deterministic order; the
    transmittance before every sample is recomputed, and the colour still to
-   come behind a sample is the final colour minus the running prefix. */
+   come behind a sample is the final colour minus the running prefix.  When
+   the context's last forward rendered the same structure build, cameras and
+   options, its recorded closest-hit results are replayed instead of
+   searched again (same values, so the same segments); calls that overlap on
+   one context race on that record. */
 rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
                                int32_t n_views, const rgx_render_opts *opts, const float *out_rgb,
                                const float *out_T, const float *grad_rgb, const float *grad_T,
@@ -244,6 +252,10 @@ rgx_status rgx_set_kernel_timing(rgx_context *ctx, int32_t enable);
    milliseconds ms[RGX_NKERN] and the number of launches launches[RGX_NKERN]
    (host arrays).  reset != 0 clears the record afterwards. */
 rgx_status rgx_kernel_times(rgx_context *ctx, double *ms, int64_t *launches, int32_t reset);
+
+/* (host) 1 if the context's last rgx_render_backward replayed the closest-hit
+   results of its forward, 0 if it searched them itself. */
+int32_t rgx_backward_replayed(const rgx_context *ctx);
 
 const char *rgx_status_string(rgx_status s);
 const char *rgx_last_error(const rgx_context *ctx);

@@ -46,6 +46,10 @@ struct rgx_context {
   size_t ev_used = 0;
   double *partial = nullptr;        // per-block partial sums of rgx_isotropic_loss
   int64_t partial_cap = 0;
+  DevBuf replay;                    // closest-hit results recorded by the last forward
+  uint64_t replay_key = 0;          // what that forward rendered (0: nothing recorded)
+  std::vector<void *> retired;      // outgrown replay buffers: a captured graph may still use them
+  int32_t replayed = 0;             // whether the last backward replayed
 };
 
 // Records hipEvents on `stream` around `launch` when timing is enabled.
@@ -79,6 +83,7 @@ struct rgx_bvh {
   float sigma_eps = 0.01f;
   int morton_bits = 21;
   int sorted_sel = 0;
+  uint64_t generation = 0;          // bumped by every build: keys the closest-hit replay
   DevBuf geom_user, aabb_user, aux_user, aux, active, bounds, counters, keys0, keys1, vals0, vals1, hist, geom,
       aabb, col, nodes, nodes4, seg, parent, acc, zprev;
 };
@@ -152,6 +157,8 @@ rgx_status rgx_create(int device, rgx_context **out) {
   return RGX_OK;
 }
 
+int32_t rgx_backward_replayed(const rgx_context *ctx) { return ctx ? ctx->replayed : 0; }
+
 void rgx_destroy(rgx_context *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
@@ -159,6 +166,8 @@ void rgx_destroy(rgx_context *ctx) {
   if (ctx->queue) (void)hipFree(ctx->queue);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->partial) (void)hipFree(ctx->partial);
+  if (ctx->replay.p) (void)hipFree(ctx->replay.p);
+  for (void *p : ctx->retired) (void)hipFree(p);
   delete ctx;
 }
 
@@ -232,6 +241,7 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
                 std::string("allocation: ") + hipGetErrorString(e));
   }
   b->n = n;
+  b->generation++;
   b->sh_degree = g->sh_degree;
   b->sh_k = sh_k;
   b->col_stride = col_stride;
@@ -294,6 +304,7 @@ static int ilog2(int v) {
 static rgx_status make_opts(rgx_context *ctx, const rgx_bvh *b, const rgx_render_opts *o,
                             MarchOpts &m) {
   if (!o) return fail(ctx, RGX_ERR_INVALID_ARG, "null opts");
+  memset(&m, 0, sizeof m);   // padding included: march_key hashes the bytes
   if (!(o->n_s == 1 || o->n_s == 2 || o->n_s == 4 || o->n_s == 8 || o->n_s == 16))
     return fail(ctx, RGX_ERR_UNSUPPORTED, "n_s must be 1, 2, 4, 8 or 16");
   if (o->adaptive) {
@@ -423,6 +434,33 @@ static rgx_status view_tables(rgx_context *ctx, const rgx_camera *cams, int n_vi
   return RGX_OK;
 }
 
+// FNV-1a over what decides a march's closest-hit queries: the structure
+// (and its build generation), the cameras and the options.
+static uint64_t march_key(const rgx_bvh *b, const rgx_camera *cams, int32_t n_views,
+                          const MarchOpts &m) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void *p, size_t n) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; i++) { h ^= c[i]; h *= 1099511628211ull; }
+  };
+  MarchOpts k;
+  memcpy(&k, &m, sizeof k);
+  k.replay_mode = 0;
+  k.replay = nullptr;
+  mix(&b, sizeof b);
+  mix(&b->generation, sizeof b->generation);
+  mix(&n_views, sizeof n_views);
+  mix(cams, sizeof(rgx_camera) * (size_t)n_views);
+  mix(&k, sizeof k);
+  return h ? h : 1;
+}
+
+static int64_t total_rays(const rgx_camera *cams, int32_t n_views) {
+  int64_t r = 0;
+  for (int v = 0; v < n_views; v++) r += (int64_t)cams[v].width * cams[v].height;
+  return r;
+}
+
 // waves_per_cu: how many of the kernel's one-wave workgroups fit on a CU
 static LaunchShape shape_for(rgx_context *ctx, const MarchOpts &m, int n_tiles, int waves_per_cu) {
   LaunchShape ls;
@@ -452,11 +490,31 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
   out.rgb = out_rgb;
   out.T = out_T;
   out.stats = stats;
+  // record the closest-hit results for a backward over the same rays; the
+  // buffer only grows, and an outgrown one stays allocated until rgx_destroy
+  // (a captured graph may hold its address)
+  const uint64_t key = march_key(bvh, cams, n_views, m);
+  ctx->replay_key = 0;
+  const size_t need = (size_t)total_rays(cams, n_views) * kReplayK * sizeof(float);
+  if (m.ess && ctx->replay.bytes < need) {
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max(need, 2 * ctx->replay.bytes)) == hipSuccess) {
+      if (ctx->replay.p) ctx->retired.push_back(ctx->replay.p);
+      ctx->replay.p = p;
+      ctx->replay.bytes = std::max(need, 2 * ctx->replay.bytes);
+    }
+    (void)hipGetLastError();   // an allocation failure only disables the replay
+  }
+  if (m.ess && ctx->replay.bytes >= need) {
+    m.replay_mode = 1;
+    m.replay = (float *)ctx->replay.p;
+  }
   for (const ViewTable &t : tabs) {
     if (t.n_tiles == 0) continue;
     HIP_TRY(ctx, timed(ctx, RGX_KERN_FORWARD, stream,
                        [&] { return launch_forward(sd, t, m, out, shape_for(ctx, m, t.n_tiles, fwd_waves_per_cu(m)), stream); }));
   }
+  if (m.replay_mode == 1) ctx->replay_key = key;
   return RGX_OK;
 }
 
@@ -476,6 +534,12 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
   if ((s = view_tables(ctx, cams, n_views, m, tabs)) != RGX_OK) return s;
   const SceneDev sd = scene_of(bvh);
   // the accumulators are zero: cleared by the build and by every finalisation
+  ctx->replayed = 0;
+  if (m.ess && ctx->replay_key != 0 && ctx->replay_key == march_key(bvh, cams, n_views, m)) {
+    m.replay_mode = 2;
+    m.replay = (float *)ctx->replay.p;
+    ctx->replayed = 1;
+  }
   BwdIn in;
   in.rgb = out_rgb;
   in.T = out_T;

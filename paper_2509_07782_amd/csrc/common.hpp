@@ -60,7 +60,12 @@ struct MarchOpts {
   float bg[3];
   int32_t sh_k;           // SH coefficients per channel
   int32_t col_stride;     // floats per packed colour record
+  // closest-hit replay: the forward records each ray's first kReplayK
+  // closest-hit results, a backward of the same rays replays them
+  int32_t replay_mode;    // 0 off, 1 record, 2 replay
+  float *replay;          // [rays of the call][kReplayK]
 };
+constexpr int kReplayK = 4;
 
 // Scalar (constant address space) views of read-only scene data: a
 // wave-uniform address loads once into SGPRs for the whole wave.

@@ -453,12 +453,18 @@ __device__ __forceinline__ float wave_max(float v) {
 // Depth-first packet traversal, nearer child first (by the smallest entry
 // over the wave's pending lanes); each lane's bound shrinks to its best hit
 // so far and prunes.  A minimum does not depend on the visiting order.
+// Query qn of ray `ray`: recorded into (or, for q < kReplayK, replayed from)
+// op.replay when op.replay_mode asks for it.
 __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts &op, int n_active,
                                              const Ray &r, float tn, float tf, float dS,
-                                             SegState &ss, int32_t *err, int32_t *st_closest) {
+                                             SegState &ss, int32_t *err, int32_t *st_closest,
+                                             int &qn, int64_t ray) {
   if (ballot(ss.pending) == 0) return;
-  const float lo = ss.pending ? ss.cl_lo : kInf;
-  float hi = ss.pending ? tf : -kInf;
+  const bool replayed = op.replay_mode == 2 && ss.pending && qn < kReplayK;
+  const float rbest = replayed ? op.replay[ray * kReplayK + qn] : kInf;
+  const bool search = ss.pending && !replayed;
+  const float lo = search ? ss.cl_lo : kInf;
+  float hi = search ? tf : -kInf;
   float best = kInf;
   auto leaf = [&](int j) {
     const Gauss g = with_origin(load_gauss(s.geom, j), r.ox, r.oy, r.oz);
@@ -468,7 +474,9 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
       hi = fminf(hi, best);
     }
   };
-  if (op.brute_force) {
+  if (ballot(search) == 0) {
+    // every pending lane replays
+  } else if (op.brute_force) {
     for (int j = 0; j < n_active; j++) leaf(j);
   } else if (n_active > 0) {
     const int n_inner = n_active > 1 ? n_active - 1 : 1;
@@ -525,6 +533,9 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
     }
   }
   if (ss.pending) {
+    if (replayed) best = rbest;
+    else if (op.replay_mode == 1 && qn < kReplayK) op.replay[ray * kReplayK + qn] = best;
+    qn++;
     if (st_closest) (*st_closest)++;
     if (!(best < kInf)) ss.alive = false;
     else restart_at(op, tn, dS, best, ss);
@@ -1372,6 +1383,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
     sh_basis(op.sh_k, r.dx, r.dy, r.dz, Y);
 
     SegState ss;
+    int n_closest = 0;   // closest-hit queries of this lane's ray so far
     ss.alive = px.valid;
     ss.pending = op.ess && px.valid;
     ss.seg_i = 0;
@@ -1404,7 +1416,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       if (stats) cyc_t0 = clock64();
       if (op.ess)
         closest_pass(s, op, n_active, r, tn, tf, dS, ss, ls.error_flag,
-                     stats ? &cnt[ST_CLOSEST] : nullptr);
+                     stats ? &cnt[ST_CLOSEST] : nullptr, n_closest, px.ray);
       if (stats) cyc_closest += clock64() - cyc_t0;
       if (ss.alive) {
         const float a0 = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
@@ -1588,6 +1600,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
     sh_batch_start(shb, sb, M.l_tin, Y, Gc0, Gc1, Gc2, lane);
     float GP = 0.0f;
     SegState ss;
+    int n_closest = 0;   // closest-hit queries of this lane's ray so far
     ss.alive = px.valid;
     ss.pending = op.ess && px.valid;
     ss.seg_i = 0;
@@ -1610,7 +1623,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
     float T = 1.0f;
 
     for (;;) {
-      if (op.ess) closest_pass(s, op, n_active, r, tn, tf, dS, ss, ls.error_flag, nullptr);
+      if (op.ess) closest_pass(s, op, n_active, r, tn, tf, dS, ss, ls.error_flag, nullptr, n_closest, px.ray);
       if (ss.alive) {
         const float a0 = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
         if (!(a0 < tf) || !(T > op.t_eps)) ss.alive = false;

@@ -58,7 +58,7 @@ class Grads(C.Structure):
 EXPORTS = ("rgx_create", "rgx_destroy", "rgx_build_bvh", "rgx_bvh_destroy", "rgx_bvh_size",
            "rgx_render_forward", "rgx_render_backward", "rgx_dump_hits", "rgx_bvh_debug",
            "rgx_error_flags", "rgx_set_kernel_timing", "rgx_kernel_times", "rgx_isotropic_loss",
-           "rgx_status_string", "rgx_last_error")
+           "rgx_backward_replayed", "rgx_status_string", "rgx_last_error")
 
 KERNEL_KINDS = ("build", "forward", "backward", "finalize")   # RGX_KERN_* order
 
@@ -103,6 +103,8 @@ def load():
     L.rgx_set_kernel_timing.restype = st
     L.rgx_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
     L.rgx_kernel_times.restype = st
+    L.rgx_backward_replayed.argtypes = [vp]
+    L.rgx_backward_replayed.restype = C.c_int32
     L.rgx_status_string.argtypes = [st]
     L.rgx_status_string.restype = C.c_char_p
     L.rgx_last_error.argtypes = [vp]
@@ -183,6 +185,10 @@ class Context:
         ms, cnt = (C.c_double * n)(), (C.c_int64 * n)()
         check(load().rgx_kernel_times(self.h, ms, cnt, int(bool(reset))), self.h, "kernel_times")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    def backward_replayed(self) -> bool:
+        """Whether the last backward replayed its forward's closest-hit results."""
+        return bool(load().rgx_backward_replayed(self.h))
 
     def error_flags(self, stream=0) -> int:
         f = C.c_int32(0)

@@ -84,6 +84,40 @@ def test_backward_sh_degrees_and_segment_sizes(torch_cuda, deg, ns):
     r.close()
 
 
+def test_closest_hit_replay(small_setup, torch_cuda):
+    """A backward right after its forward replays the recorded closest-hit
+    results; after a forward of other rays, or after a rebuild, it searches
+    them itself.  Both give the same gradients (the same restarts)."""
+    torch = torch_cuda
+    sc, cam, r, params, gC, gT = small_setup
+    o = _opts(adaptive=True, ess=1, t_eps=1e-4)
+    other = inputs.look_at_camera(21, 17, (-0.4, 0.3, 2.5), fov_deg=40.0)
+    gCt = torch.from_numpy(gC).cuda()
+    rgb, T = r.forward([cam], o)
+    g_rep = r.backward([cam], o, rgb, T, gCt, None, params)
+    torch.cuda.synchronize()
+    assert r.ctx.backward_replayed()
+    r.forward([other], o)                      # the record now holds other rays
+    g_own = r.backward([cam], o, rgb, T, gCt, None, params)
+    torch.cuda.synchronize()
+    assert not r.ctx.backward_replayed()
+    for k in PARAM_KEYS:
+        a, b = g_rep[k].cpu().numpy(), g_own[k].cpu().numpy()
+        d = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert d <= 1e-5, (k, d)
+    r.forward([cam], o)
+    r.build(params, sc["sh_degree"], force=True)   # a new build invalidates the record
+    r.backward([cam], o, rgb, T, gCt, None, params)
+    torch.cuda.synchronize()
+    assert not r.ctx.backward_replayed()
+    # no empty-space skipping: nothing recorded, nothing replayed
+    o2 = _opts(dt=0.005, ess=0)
+    rgb2, T2 = r.forward([cam], o2)
+    r.backward([cam], o2, rgb2, T2, gCt, None, params)
+    torch.cuda.synchronize()
+    assert not r.ctx.backward_replayed()
+
+
 def test_backward_bvh_equals_brute_force(small_setup, torch_cuda):
     sc, cam, r, params, gC, gT = small_setup
     a = _gpu_grads(torch_cuda, r, cam, _opts(dt=0.005, brute_force=True), params, gC, gT)
