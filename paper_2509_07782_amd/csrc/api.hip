@@ -47,6 +47,7 @@ struct rgx_context {
   double *partial = nullptr;        // per-block partial sums of rgx_isotropic_loss
   int64_t partial_cap = 0;
   DevBuf replay;                    // closest-hit results recorded by the last forward
+  DevBuf wrec;                      // its window lists, kWrecDwords per tile
   uint64_t replay_key = 0;          // what that forward rendered (0: nothing recorded)
   std::vector<void *> retired;      // outgrown replay buffers: a captured graph may still use them
   int32_t replayed = 0;             // whether the last backward replayed
@@ -167,6 +168,7 @@ void rgx_destroy(rgx_context *ctx) {
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->partial) (void)hipFree(ctx->partial);
   if (ctx->replay.p) (void)hipFree(ctx->replay.p);
+  if (ctx->wrec.p) (void)hipFree(ctx->wrec.p);
   for (void *p : ctx->retired) (void)hipFree(p);
   delete ctx;
 }
@@ -387,9 +389,9 @@ static rgx_status tile_order(rgx_context *ctx, int W, int H, int tw, int th, con
 // Split the views into launches of at most kMaxViewsPerLaunch.
 static rgx_status view_tables(rgx_context *ctx, const rgx_camera *cams, int n_views,
                               const MarchOpts &m, std::vector<ViewTable> &tabs,
-                              int64_t ray0 = 0) {
+                              int64_t ray0 = 0, int64_t tile0 = 0) {
   if (!cams || n_views <= 0) return fail(ctx, RGX_ERR_INVALID_ARG, "no views");
-  int64_t ray = ray0;
+  int64_t ray = ray0, tile_base = tile0;
   for (int v0 = 0; v0 < n_views; v0 += kMaxViewsPerLaunch) {
     ViewTable t;
     memset(&t, 0, sizeof t);
@@ -429,6 +431,9 @@ static rgx_status view_tables(rgx_context *ctx, const rgx_camera *cams, int n_vi
       V.t_far = c.t_far;
     }
     t.n_tiles = tiles;
+    if (tile_base > INT32_MAX - tiles) return fail(ctx, RGX_ERR_INVALID_ARG, "too many tiles in one call");
+    t.tile0 = (int32_t)tile_base;
+    tile_base += tiles;
     tabs.push_back(t);
   }
   return RGX_OK;
@@ -453,6 +458,22 @@ static uint64_t march_key(const rgx_bvh *b, const rgx_camera *cams, int32_t n_vi
   mix(cams, sizeof(rgx_camera) * (size_t)n_views);
   mix(&k, sizeof k);
   return h ? h : 1;
+}
+
+// Grows a record buffer to at least `need` bytes; an outgrown buffer is kept
+// until rgx_destroy (a captured graph may hold its address).
+static bool grow_record(rgx_context *ctx, DevBuf &b, size_t need) {
+  if (b.bytes >= need) return true;
+  void *p = nullptr;
+  const size_t bytes = std::max(need, 2 * b.bytes);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();   // an allocation failure only disables the replay
+    return false;
+  }
+  if (b.p) ctx->retired.push_back(b.p);
+  b.p = p;
+  b.bytes = bytes;
+  return true;
 }
 
 static int64_t total_rays(const rgx_camera *cams, int32_t n_views) {
@@ -495,19 +516,15 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
   // (a captured graph may hold its address)
   const uint64_t key = march_key(bvh, cams, n_views, m);
   ctx->replay_key = 0;
+  int64_t tiles = 0;
+  for (const ViewTable &t : tabs) tiles += t.n_tiles;
   const size_t need = (size_t)total_rays(cams, n_views) * kReplayK * sizeof(float);
-  if (m.ess && ctx->replay.bytes < need) {
-    void *p = nullptr;
-    if (hipMalloc(&p, std::max(need, 2 * ctx->replay.bytes)) == hipSuccess) {
-      if (ctx->replay.p) ctx->retired.push_back(ctx->replay.p);
-      ctx->replay.p = p;
-      ctx->replay.bytes = std::max(need, 2 * ctx->replay.bytes);
-    }
-    (void)hipGetLastError();   // an allocation failure only disables the replay
-  }
-  if (m.ess && ctx->replay.bytes >= need) {
+  const size_t need_w = (size_t)tiles * kWrecDwords * sizeof(uint32_t);
+  if (m.ess && !m.brute_force && grow_record(ctx, ctx->replay, need) &&
+      grow_record(ctx, ctx->wrec, need_w)) {
     m.replay_mode = 1;
     m.replay = (float *)ctx->replay.p;
+    m.wrec = (uint32_t *)ctx->wrec.p;
   }
   for (const ViewTable &t : tabs) {
     if (t.n_tiles == 0) continue;
@@ -535,9 +552,11 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
   const SceneDev sd = scene_of(bvh);
   // the accumulators are zero: cleared by the build and by every finalisation
   ctx->replayed = 0;
-  if (m.ess && ctx->replay_key != 0 && ctx->replay_key == march_key(bvh, cams, n_views, m)) {
+  if (m.ess && !m.brute_force && ctx->replay_key != 0 &&
+      ctx->replay_key == march_key(bvh, cams, n_views, m)) {
     m.replay_mode = 2;
     m.replay = (float *)ctx->replay.p;
+    m.wrec = (uint32_t *)ctx->wrec.p;
     ctx->replayed = 1;
   }
   BwdIn in;
@@ -559,11 +578,12 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
     rgx_bvh *mb = const_cast<rgx_bvh *>(bvh);
     HIP_TRY(ctx, ensure(mb->zprev, (size_t)bvh->n * 3 * sizeof(float)));
     HIP_TRY(ctx, launch_fill(mb->zprev.p, bvh->n * 3, 0u, stream));
-    int64_t ray0 = 0;
+    int64_t ray0 = 0, tile0 = 0;
     for (int v = 0; v < n_views; v++) {
       std::vector<ViewTable> one;
-      if ((s = view_tables(ctx, cams + v, 1, m, one, ray0)) != RGX_OK) return s;
+      if ((s = view_tables(ctx, cams + v, 1, m, one, ray0, tile0)) != RGX_OK) return s;
       ray0 += (int64_t)cams[v].width * cams[v].height;
+      tile0 += one[0].n_tiles;
       for (const ViewTable &t : one) {
         if (t.n_tiles == 0) continue;
         HIP_TRY(ctx, timed(ctx, RGX_KERN_BACKWARD, stream,

@@ -43,6 +43,7 @@ struct View {
 struct ViewTable {
   int32_t n_views;
   int32_t n_tiles;        // total tiles over the views of this launch
+  int32_t tile0;          // index of this launch's first tile among all tiles of the call
   View v[kMaxViewsPerLaunch];
 };
 
@@ -64,8 +65,15 @@ struct MarchOpts {
   // closest-hit results, a backward of the same rays replays them
   int32_t replay_mode;    // 0 off, 1 record, 2 replay
   float *replay;          // [rays of the call][kReplayK]
+  uint32_t *wrec;         // window-list record: kWrecDwords per tile of the call
 };
 constexpr int kReplayK = 4;
+// Window-list record of one tile: [0] 1 if complete, [1] dwords used, [2..3]
+// unused, then per collection a header (count returned, paused, z0, z1, zp,
+// list size) and that many (id, t_in, t_out) entries in Z order.  A tile
+// whose collections do not fit is marked incomplete and not replayed.
+constexpr int kWrecDwords = 12288;
+constexpr int kWrecHead = 4;
 
 // Scalar (constant address space) views of read-only scene data: a
 // wave-uniform address loads once into SGPRs for the whole wave.

@@ -1234,6 +1234,96 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
   }
 }
 
+// Window-list record of a tile (layout next to kWrecDwords): a forward
+// appends every collection's sorted chunk and the collection state its
+// callers read; a backward of the same rays reads them back in the same
+// order instead of walking the tree.
+struct WinRec {
+  uint32_t *base = nullptr;   // the tile's region
+  int off = kWrecHead;        // cursor (dwords)
+  bool ok = false;            // record: still within the region; replay: tile complete
+};
+
+__device__ __forceinline__ void rec_start(WinRec &R, const MarchOpts &op, const ViewTable &vt,
+                                          int w) {
+  R.off = kWrecHead;
+  R.base = op.replay_mode ? op.wrec + (size_t)kWrecDwords * (size_t)(vt.tile0 + w) : nullptr;
+  if (op.replay_mode == 1) R.ok = true;
+  else if (op.replay_mode == 2) R.ok = uniform_int((int)R.base[0]) == 1;
+  else R.ok = false;
+}
+
+// forward: the tile's status once all its collections are in
+__device__ __forceinline__ void rec_finish(WinRec &R, const MarchOpts &op, int lane) {
+  if (op.replay_mode != 1) return;
+  if (lane == 0) {
+    R.base[0] = R.ok ? 1u : 0u;
+    R.base[1] = (uint32_t)R.off;
+  }
+}
+
+__device__ __forceinline__ void rec_put(WinRec &R, const WaveMem &M, const Trav &t, int cnt,
+                                        int lane) {
+  if (!R.ok) return;
+  const int n = cnt > 0 ? cnt : 0;
+  if (R.off + 6 + 3 * n > kWrecDwords) { R.ok = false; return; }
+  uint32_t *p = R.base + R.off;
+  if (lane == 0) {
+    p[0] = (uint32_t)cnt; p[1] = t.paused ? 1u : 0u; p[2] = (uint32_t)t.z0;
+    p[3] = (uint32_t)t.z1; p[4] = (uint32_t)t.zp; p[5] = (uint32_t)t.count;
+  }
+  for (int e = lane; e < n; e += 64) {
+    const int o = M.order[e] & (kOrderMark - 1);
+    p[6 + 3 * e] = (uint32_t)M.l_id[o];
+    p[7 + 3 * e] = __float_as_uint(M.l_tin[o]);
+    p[8 + 3 * e] = __float_as_uint(M.l_tout[o]);
+  }
+  R.off += 6 + 3 * n;
+}
+
+// Loads the chunk at dword `off` into the list (identity order); returns its
+// collection's result and the next chunk's offset in *next.
+__device__ __forceinline__ int rec_load(const WinRec &R, WaveMem &M, int off, int lane, int *next) {
+  const uint32_t *p = R.base + off;
+  const int cnt = uniform_int((int)p[0]);
+  const int n = cnt > 0 ? cnt : 0;
+  __builtin_amdgcn_wave_barrier();
+  for (int e = lane; e < n; e += 64) {
+    M.l_id[e] = (int)p[6 + 3 * e];
+    M.l_tin[e] = __uint_as_float(p[7 + 3 * e]);
+    M.l_tout[e] = __uint_as_float(p[8 + 3 * e]);
+    M.order[e] = e;
+  }
+  __builtin_amdgcn_wave_barrier();
+  *next = off + 6 + 3 * n;
+  return cnt;
+}
+
+// One collection: the tree walk (recorded in a recording forward) or, in a
+// replaying backward of a complete tile, the recorded chunk and state.
+// *start receives the chunk's record offset.
+__device__ __forceinline__ int collect(const SceneDev &s, const MarchOpts &op, WaveMem &M,
+                                       const Ray &r, int lane, Trav &t, int n_active, bool stats,
+                                       int32_t *err, int32_t &nodes, int32_t &leaves,
+                                       int64_t *cyc_excl, WinRec &R, int *start) {
+  *start = R.off;
+  if (op.replay_mode == 2 && R.ok) {
+    const uint32_t *p = R.base + R.off;
+    t.paused = uniform_int((int)p[1]) != 0;
+    t.z0 = uniform_int((int)p[2]);
+    t.z1 = uniform_int((int)p[3]);
+    t.zp = uniform_int((int)p[4]);
+    t.count = uniform_int((int)p[5]);
+    int next;
+    const int cnt = rec_load(R, M, R.off, lane, &next);
+    R.off = next;
+    return cnt;
+  }
+  const int cnt = trav_run(s, M, r, lane, t, n_active, stats, err, nodes, leaves, cyc_excl);
+  if (op.replay_mode == 1) rec_put(R, M, t, cnt, lane);
+  return cnt;
+}
+
 // Per-wave window bookkeeping shared by forward and backward.
 struct Window {
   float len, len_min, len_max;   // uniform window length beyond the segment, and its bounds
@@ -1243,6 +1333,7 @@ struct Window {
   int kind;                      // SourceKind of the current candidates
   bool chunked;                  // uniform: this segment's candidates come in Z chunks
   int zend;                      // uniform end of the Z range the chunks cover
+  int rec_first, rec_last;       // record offsets of the segment's first and last chunk
   Trav t;                        // the collection behind the list
 };
 
@@ -1254,7 +1345,7 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
                                               const Ray &r, int lane, int n_active, bool alive,
                                               float a, float b, Window &w, bool stats,
                                               int32_t *err, int32_t &nodes, int32_t &leaves,
-                                              int32_t &windows, bool &fits,
+                                              int32_t &windows, bool &fits, WinRec &R,
                                               int64_t *cyc_excl = nullptr) {
   if (op.brute_force) {
     w.kind = SRC_BRUTE;
@@ -1274,7 +1365,9 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
   windows++;
   trav_start(M, lane, w.t, rays, 0, n_active);
   w.zend = n_active;
-  const int cnt = trav_run(s, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl);
+  const int cnt = collect(s, op, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl, R,
+                          &w.rec_first);
+  w.rec_last = w.rec_first;
   w.kind = SRC_LIST;
   w.count = cnt > 0 ? cnt : 0;   // a malformed tree ends the rays (error flag set)
   w.chunked = cnt >= 0 && (w.t.paused || w.t.z1 < n_active);
@@ -1309,14 +1402,14 @@ __device__ __forceinline__ void first_chunk(const SceneDev &s, WaveMem &M, const
 // paused collection, or after a cut at z1 collects again from z1 for the
 // lanes in `lanes` over their segments [a, b].  False when the segment's
 // candidates are exhausted.
-__device__ __forceinline__ bool next_chunk(const SceneDev &s, WaveMem &M, const Ray &r, int lane,
-                                           int n_active, bool lanes, float a, float b, Window &w,
-                                           bool stats, int32_t *err, int32_t &nodes,
-                                           int32_t &leaves, int32_t &windows,
-                                           int64_t *cyc_excl = nullptr) {
+__device__ __forceinline__ bool next_chunk(const SceneDev &s, const MarchOpts &op, WaveMem &M,
+                                           const Ray &r, int lane, int n_active, bool lanes,
+                                           float a, float b, Window &w, bool stats, int32_t *err,
+                                           int32_t &nodes, int32_t &leaves, int32_t &windows,
+                                           WinRec &R, int64_t *cyc_excl = nullptr) {
   if (!w.chunked) return false;
   if (w.t.paused) {
-    trav_advance(M, lane, w.t);
+    if (!(op.replay_mode == 2 && R.ok)) trav_advance(M, lane, w.t);
   } else {
     if (w.t.z1 >= w.zend) return false;
     const uint64_t rays = ballot(lanes);
@@ -1326,7 +1419,8 @@ __device__ __forceinline__ bool next_chunk(const SceneDev &s, WaveMem &M, const 
     windows++;
     trav_start(M, lane, w.t, rays, w.t.z1, w.zend);
   }
-  const int cnt = trav_run(s, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl);
+  const int cnt = collect(s, op, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl, R,
+                          &w.rec_last);
   if (cnt < 0) {
     w.count = 0;
     w.chunked = false;
@@ -1384,6 +1478,8 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
 
     SegState ss;
     int n_closest = 0;   // closest-hit queries of this lane's ray so far
+    WinRec rec;
+    rec_start(rec, op, vt, w);
     ss.alive = px.valid;
     ss.pending = op.ess && px.valid;
     ss.seg_i = 0;
@@ -1435,7 +1531,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       bool go;
       if (stats) cyc_t0 = clock64();
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
-                    cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS], go,
+                    cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS], go, rec,
                     stats ? &cyc_boxstat : nullptr);
       if (stats) cyc_collect += clock64() - cyc_t0;
       if (stats && go && win.chunked) cnt[ST_CHUNKED]++;
@@ -1479,9 +1575,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         }
       }); while ([&] {
         if (stats) cyc_t0 = clock64();
-        const bool more = next_chunk(s, M, r, lane, n_active, go, a, b, win, stats,
+        const bool more = next_chunk(s, op, M, r, lane, n_active, go, a, b, win, stats,
                                      ls.error_flag, cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS],
-                                     stats ? &cyc_boxstat : nullptr);
+                                     rec, stats ? &cyc_boxstat : nullptr);
         if (stats) cyc_collect += clock64() - cyc_t0;
         return more;
       }());
@@ -1524,6 +1620,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       }
     }
 
+    rec_finish(rec, op, lane);
     if (stats) {
       cnt[ST_BOX_ONLY] += M.cnt_box[lane];
       cnt[ST_KCYC_COLLECT] = (int32_t)((cyc_collect - cyc_boxstat) >> 10);
@@ -1601,6 +1698,8 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
     float GP = 0.0f;
     SegState ss;
     int n_closest = 0;   // closest-hit queries of this lane's ray so far
+    WinRec rec;
+    rec_start(rec, op, vt, w);
     ss.alive = px.valid;
     ss.pending = op.ess && px.valid;
     ss.seg_i = 0;
@@ -1640,7 +1739,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
       if (!ss.alive) { sp.t0 = 0.0f; sp.dt = 0.0f; }
       bool go;
       ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, false, ls.error_flag,
-                    dummy_nodes, dummy_leaves, dummy_windows, go);
+                    dummy_nodes, dummy_leaves, dummy_windows, go, rec);
       const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
       const float lo = go ? a : kInf, hi = go ? b : -kInf;
       // only G . W_k enters the adjoints, so pass A sums the Gaussians'
@@ -1672,8 +1771,8 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
           }
         }
         return true;
-      }); while (next_chunk(s, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
-                            dummy_nodes, dummy_leaves, dummy_windows));
+      }); while (next_chunk(s, op, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
+                            dummy_nodes, dummy_leaves, dummy_windows, rec));
 
       // per-sample adjoints: dL/dsigma_k (into sg) and T_k phi_k (into GW);
       // dL/dW_k is G T_k phi_k
@@ -1769,12 +1868,21 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
         const int zlast = win.chunked ? win.t.z0 : 0;
         for_each_candidate<CAND_FILTER>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
                                         pass_b);
-        if (win.chunked && zlast > 0) {
+        if (win.chunked && zlast > 0 && rec.ok) {
+          // replaying: the segment's earlier chunks come from the record
+          for (int off = win.rec_first; off < win.rec_last;) {
+            int next;
+            const int c = rec_load(rec, M, off, lane, &next);
+            off = next;
+            for_each_candidate(SRC_LIST, s, M, c > 0 ? c : 0, lane, a_min, b_max, n_active, r,
+                               pass_b);
+          }
+        } else if (win.chunked && zlast > 0) {
           first_chunk(s, M, r, lane, n_active, any, a, b, zlast, win, false, ls.error_flag,
                       dummy_nodes, dummy_leaves, dummy_windows);
           do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, pass_b);
-          while (next_chunk(s, M, r, lane, n_active, any, a, b, win, false, ls.error_flag,
-                            dummy_nodes, dummy_leaves, dummy_windows));
+          while (next_chunk(s, op, M, r, lane, n_active, any, a, b, win, false, ls.error_flag,
+                            dummy_nodes, dummy_leaves, dummy_windows, rec));
         }
       }
 
