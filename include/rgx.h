@@ -168,10 +168,12 @@ int64_t rgx_bvh_size(const rgx_bvh *bvh);
 /* Forward render of n_views views (host array) through Algorithm 1.
    out_rgb [R,3] and out_T [R] with R = sum of width*height; `stats`
    (nullable) receives [R, RGX_NSTAT] int32 counters.  With empty-space
-   skipping on, the forward also records each ray's first four closest-hit
-   results (Alg. 1 ClosestHit, Eq. 4) in a context-owned buffer (16 B per
-   ray, grown on demand; outgrown buffers are kept until rgx_destroy), keyed
-   by the structure, its build, the cameras and the options. */
+   skipping on (and the BVH in use), the forward also records, keyed by the
+   structure, its build, the cameras and the options, in context-owned
+   buffers grown on demand (outgrown ones are kept until rgx_destroy):
+   each ray's first four closest-hit results (Alg. 1 ClosestHit, Eq. 4;
+   16 B per ray) and every window list its tiles collected (a shared pool of
+   48 KB per 64-ray tile; a tile that does not fit is not recorded). */
 rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
                               int32_t n_views, const rgx_render_opts *opts, float *out_rgb,
                               float *out_T, int32_t *stats, hipStream_t stream);
@@ -184,9 +186,9 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
    transmittance before every sample is recomputed, and the colour still to
    come behind a sample is the final colour minus the running prefix.  When
    the context's last forward rendered the same structure build, cameras and
-   options, its recorded closest-hit results are replayed instead of
-   searched again (same values, so the same segments); calls that overlap on
-   one context race on that record. */
+   options, its recorded closest-hit results and window lists are replayed
+   instead of searched again (same values, so the same segments); calls that
+   overlap on one context race on that record. */
 rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
                                int32_t n_views, const rgx_render_opts *opts, const float *out_rgb,
                                const float *out_T, const float *grad_rgb, const float *grad_T,
@@ -220,8 +222,10 @@ rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *bvh, uint64_t *keys, i
                          float *aabb, float *nodes, float *nodes4, int64_t *n_active,
                          hipStream_t stream);
 
-/* Debug: device-side error flags of the context (synchronises the stream).
-   flags[0] != 0 means a traversal exceeded its stack (results invalid). */
+/* Debug: device-side error flag of the context (synchronises the stream).
+   flags[0] != 0 means results are invalid: 1 a closest-hit stack overflowed,
+   2 a traversal visited more nodes than the tree has, 3 a malformed node,
+   4 a segment made no progress in FP32, 5 a broken window-list record. */
 rgx_status rgx_error_flags(rgx_context *ctx, int32_t *flags /*host*/, hipStream_t stream);
 
 /* Isotropic scale loss (Sec. 3.4, Eq. 8, with the volume-ratio bound of

@@ -47,7 +47,8 @@ struct rgx_context {
   double *partial = nullptr;        // per-block partial sums of rgx_isotropic_loss
   int64_t partial_cap = 0;
   DevBuf replay;                    // closest-hit results recorded by the last forward
-  DevBuf wrec;                      // its window lists, kWrecDwords per tile
+  DevBuf wrec;                      // its window lists (shared pool, counter first)
+  DevBuf wrec_tile;                 // per tile: (complete, first chunk)
   uint64_t replay_key = 0;          // what that forward rendered (0: nothing recorded)
   std::vector<void *> retired;      // outgrown replay buffers: a captured graph may still use them
   int32_t replayed = 0;             // whether the last backward replayed
@@ -169,6 +170,7 @@ void rgx_destroy(rgx_context *ctx) {
   if (ctx->partial) (void)hipFree(ctx->partial);
   if (ctx->replay.p) (void)hipFree(ctx->replay.p);
   if (ctx->wrec.p) (void)hipFree(ctx->wrec.p);
+  if (ctx->wrec_tile.p) (void)hipFree(ctx->wrec_tile.p);
   for (void *p : ctx->retired) (void)hipFree(p);
   delete ctx;
 }
@@ -519,12 +521,18 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
   int64_t tiles = 0;
   for (const ViewTable &t : tabs) tiles += t.n_tiles;
   const size_t need = (size_t)total_rays(cams, n_views) * kReplayK * sizeof(float);
-  const size_t need_w = (size_t)tiles * kWrecDwords * sizeof(uint32_t);
+  const size_t pool = std::min<size_t>(1 + (size_t)tiles * kWrecDwordsPerTile, 0xfffffff0u);
   if (m.ess && !m.brute_force && grow_record(ctx, ctx->replay, need) &&
-      grow_record(ctx, ctx->wrec, need_w)) {
+      grow_record(ctx, ctx->wrec, pool * sizeof(uint32_t)) &&
+      grow_record(ctx, ctx->wrec_tile, (size_t)tiles * 2 * sizeof(uint32_t))) {
     m.replay_mode = 1;
     m.replay = (float *)ctx->replay.p;
     m.wrec = (uint32_t *)ctx->wrec.p;
+    m.wrec_tile = (uint32_t *)ctx->wrec_tile.p;
+    m.wrec_cap = (uint32_t)pool;
+    // the pool's allocation counter starts past itself (a fill kernel, not a
+    // memset node, so the call can be captured)
+    HIP_TRY(ctx, launch_fill(ctx->wrec.p, 1, 1u, stream));
   }
   for (const ViewTable &t : tabs) {
     if (t.n_tiles == 0) continue;
@@ -557,6 +565,8 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
     m.replay_mode = 2;
     m.replay = (float *)ctx->replay.p;
     m.wrec = (uint32_t *)ctx->wrec.p;
+    m.wrec_tile = (uint32_t *)ctx->wrec_tile.p;
+    m.wrec_cap = (uint32_t)std::min<size_t>(ctx->wrec.bytes / sizeof(uint32_t), 0xfffffff0u);
     ctx->replayed = 1;
   }
   BwdIn in;

@@ -65,15 +65,19 @@ struct MarchOpts {
   // closest-hit results, a backward of the same rays replays them
   int32_t replay_mode;    // 0 off, 1 record, 2 replay
   float *replay;          // [rays of the call][kReplayK]
-  uint32_t *wrec;         // window-list record: kWrecDwords per tile of the call
+  uint32_t *wrec;         // window-list record pool: [0] allocation counter, chunks after
+  uint32_t *wrec_tile;    // per tile of the call: (complete, first chunk offset)
+  uint32_t wrec_cap;      // pool size in dwords
 };
 constexpr int kReplayK = 4;
-// Window-list record of one tile: [0] 1 if complete, [1] dwords used, [2..3]
-// unused, then per collection a header (count returned, paused, z0, z1, zp,
-// list size) and that many (id, t_in, t_out) entries in Z order.  A tile
-// whose collections do not fit is marked incomplete and not replayed.
-constexpr int kWrecDwords = 12288;
-constexpr int kWrecHead = 4;
+// Window-list record: every collection of a tile appends one chunk to a
+// shared pool (offsets in dwords): a header (count returned, paused, z0, z1,
+// zp, list size, offset of the tile's next chunk) and that many (id, t_in,
+// t_out) entries in Z order.  A tile whose chunks do not all fit is marked
+// incomplete and is not replayed.
+constexpr int kWrecHeader = 7;
+constexpr uint32_t kWrecNone = 0xffffffffu;
+constexpr int kWrecDwordsPerTile = 12288;   // pool size per tile of the call (average)
 
 // Scalar (constant address space) views of read-only scene data: a
 // wave-uniform address loads once into SGPRs for the whole wave.

@@ -1234,68 +1234,87 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
   }
 }
 
-// Window-list record of a tile (layout next to kWrecDwords): a forward
+// Window-list record of a tile (layout next to kWrecHeader): a forward
 // appends every collection's sorted chunk and the collection state its
 // callers read; a backward of the same rays reads them back in the same
 // order instead of walking the tree.
 struct WinRec {
-  uint32_t *base = nullptr;   // the tile's region
-  int off = kWrecHead;        // cursor (dwords)
-  bool ok = false;            // record: still within the region; replay: tile complete
+  uint32_t *slot = nullptr;   // the tile's (complete, first chunk) pair
+  uint32_t cur = kWrecNone;   // replay: next chunk to read; record: last chunk written
+  uint32_t first = kWrecNone; // record: first chunk
+  bool ok = false;            // record: nothing dropped so far; replay: tile complete
 };
 
 __device__ __forceinline__ void rec_start(WinRec &R, const MarchOpts &op, const ViewTable &vt,
                                           int w) {
-  R.off = kWrecHead;
-  R.base = op.replay_mode ? op.wrec + (size_t)kWrecDwords * (size_t)(vt.tile0 + w) : nullptr;
-  if (op.replay_mode == 1) R.ok = true;
-  else if (op.replay_mode == 2) R.ok = uniform_int((int)R.base[0]) == 1;
-  else R.ok = false;
+  R.slot = op.replay_mode ? op.wrec_tile + 2 * (size_t)(vt.tile0 + w) : nullptr;
+  R.cur = kWrecNone;
+  R.first = kWrecNone;
+  R.ok = false;
+  if (op.replay_mode == 1) {
+    R.ok = true;
+  } else if (op.replay_mode == 2) {
+    R.ok = uniform_int((int)R.slot[0]) == 1;
+    R.cur = (uint32_t)uniform_int((int)R.slot[1]);
+  }
 }
 
 // forward: the tile's status once all its collections are in
 __device__ __forceinline__ void rec_finish(WinRec &R, const MarchOpts &op, int lane) {
   if (op.replay_mode != 1) return;
   if (lane == 0) {
-    R.base[0] = R.ok ? 1u : 0u;
-    R.base[1] = (uint32_t)R.off;
+    R.slot[0] = R.ok ? 1u : 0u;
+    R.slot[1] = R.first;
   }
 }
 
-__device__ __forceinline__ void rec_put(WinRec &R, const WaveMem &M, const Trav &t, int cnt,
-                                        int lane) {
+__device__ __forceinline__ void rec_put(WinRec &R, const MarchOpts &op, const WaveMem &M,
+                                        const Trav &t, int cnt, int lane) {
   if (!R.ok) return;
   const int n = cnt > 0 ? cnt : 0;
-  if (R.off + 6 + 3 * n > kWrecDwords) { R.ok = false; return; }
-  uint32_t *p = R.base + R.off;
+  const uint32_t size = kWrecHeader + 3 * n;
+  uint32_t off = 0;
+  if (lane == 0) off = atomicAdd(op.wrec, size);
+  off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
+  if ((uint64_t)off + size > op.wrec_cap) { R.ok = false; return; }
+  uint32_t *p = op.wrec + off;
   if (lane == 0) {
     p[0] = (uint32_t)cnt; p[1] = t.paused ? 1u : 0u; p[2] = (uint32_t)t.z0;
-    p[3] = (uint32_t)t.z1; p[4] = (uint32_t)t.zp; p[5] = (uint32_t)t.count;
+    p[3] = (uint32_t)t.z1; p[4] = (uint32_t)t.zp; p[5] = (uint32_t)t.count; p[6] = kWrecNone;
+    if (R.cur != kWrecNone) op.wrec[R.cur + 6] = off;   // link from the tile's previous chunk
   }
   for (int e = lane; e < n; e += 64) {
     const int o = M.order[e] & (kOrderMark - 1);
-    p[6 + 3 * e] = (uint32_t)M.l_id[o];
-    p[7 + 3 * e] = __float_as_uint(M.l_tin[o]);
-    p[8 + 3 * e] = __float_as_uint(M.l_tout[o]);
+    p[kWrecHeader + 3 * e] = (uint32_t)M.l_id[o];
+    p[kWrecHeader + 3 * e + 1] = __float_as_uint(M.l_tin[o]);
+    p[kWrecHeader + 3 * e + 2] = __float_as_uint(M.l_tout[o]);
   }
-  R.off += 6 + 3 * n;
+  if (R.first == kWrecNone) R.first = off;
+  R.cur = off;
 }
 
-// Loads the chunk at dword `off` into the list (identity order); returns its
-// collection's result and the next chunk's offset in *next.
-__device__ __forceinline__ int rec_load(const WinRec &R, WaveMem &M, int off, int lane, int *next) {
-  const uint32_t *p = R.base + off;
+// Loads the chunk at pool offset `off` into the list (identity order);
+// returns its collection's result and the tile's next chunk in *next.
+__device__ __forceinline__ int rec_load(const MarchOpts &op, WaveMem &M, uint32_t off, int lane,
+                                        uint32_t *next) {
+  // a record always fits the pool and the list; anything else is reported
+  if (off >= op.wrec_cap || op.wrec_cap - off < (uint32_t)kWrecHeader) { *next = kWrecNone; return -1; }
+  const uint32_t *p = op.wrec + off;
   const int cnt = uniform_int((int)p[0]);
   const int n = cnt > 0 ? cnt : 0;
+  if (n > kListCap || (uint64_t)off + kWrecHeader + 3 * (uint64_t)n > op.wrec_cap) {
+    *next = kWrecNone;
+    return -1;
+  }
   __builtin_amdgcn_wave_barrier();
   for (int e = lane; e < n; e += 64) {
-    M.l_id[e] = (int)p[6 + 3 * e];
-    M.l_tin[e] = __uint_as_float(p[7 + 3 * e]);
-    M.l_tout[e] = __uint_as_float(p[8 + 3 * e]);
+    M.l_id[e] = (int)p[kWrecHeader + 3 * e];
+    M.l_tin[e] = __uint_as_float(p[kWrecHeader + 3 * e + 1]);
+    M.l_tout[e] = __uint_as_float(p[kWrecHeader + 3 * e + 2]);
     M.order[e] = e;
   }
   __builtin_amdgcn_wave_barrier();
-  *next = off + 6 + 3 * n;
+  *next = (uint32_t)uniform_int((int)p[6]);
   return cnt;
 }
 
@@ -1305,22 +1324,31 @@ __device__ __forceinline__ int rec_load(const WinRec &R, WaveMem &M, int off, in
 __device__ __forceinline__ int collect(const SceneDev &s, const MarchOpts &op, WaveMem &M,
                                        const Ray &r, int lane, Trav &t, int n_active, bool stats,
                                        int32_t *err, int32_t &nodes, int32_t &leaves,
-                                       int64_t *cyc_excl, WinRec &R, int *start) {
-  *start = R.off;
+                                       int64_t *cyc_excl, WinRec &R, uint32_t *start) {
   if (op.replay_mode == 2 && R.ok) {
-    const uint32_t *p = R.base + R.off;
+    if (R.cur == kWrecNone || R.cur >= op.wrec_cap ||
+        op.wrec_cap - R.cur < (uint32_t)kWrecHeader) {   // a broken record: cannot happen
+      if (err) *err = 5;
+      t.count = 0;
+      t.paused = false;
+      return -1;
+    }
+    const uint32_t *p = op.wrec + R.cur;
     t.paused = uniform_int((int)p[1]) != 0;
     t.z0 = uniform_int((int)p[2]);
     t.z1 = uniform_int((int)p[3]);
     t.zp = uniform_int((int)p[4]);
     t.count = uniform_int((int)p[5]);
-    int next;
-    const int cnt = rec_load(R, M, R.off, lane, &next);
-    R.off = next;
+    *start = R.cur;
+    uint32_t next;
+    const int cnt = rec_load(op, M, R.cur, lane, &next);
+    if (cnt < 0 && err) *err = 5;
+    R.cur = next;
     return cnt;
   }
   const int cnt = trav_run(s, M, r, lane, t, n_active, stats, err, nodes, leaves, cyc_excl);
-  if (op.replay_mode == 1) rec_put(R, M, t, cnt, lane);
+  if (op.replay_mode == 1) rec_put(R, op, M, t, cnt, lane);
+  *start = R.cur;
   return cnt;
 }
 
@@ -1333,7 +1361,7 @@ struct Window {
   int kind;                      // SourceKind of the current candidates
   bool chunked;                  // uniform: this segment's candidates come in Z chunks
   int zend;                      // uniform end of the Z range the chunks cover
-  int rec_first, rec_last;       // record offsets of the segment's first and last chunk
+  uint32_t rec_first, rec_last;  // record offsets of the segment's first and last chunk
   Trav t;                        // the collection behind the list
 };
 
@@ -1870,9 +1898,9 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
                                         pass_b);
         if (win.chunked && zlast > 0 && rec.ok) {
           // replaying: the segment's earlier chunks come from the record
-          for (int off = win.rec_first; off < win.rec_last;) {
-            int next;
-            const int c = rec_load(rec, M, off, lane, &next);
+          for (uint32_t off = win.rec_first; off != win.rec_last && off != kWrecNone;) {
+            uint32_t next;
+            const int c = rec_load(op, M, off, lane, &next);
             off = next;
             for_each_candidate(SRC_LIST, s, M, c > 0 ? c : 0, lane, a_min, b_max, n_active, r,
                                pass_b);
