@@ -99,7 +99,7 @@ typedef struct {
   int32_t ray_order;         /* 0: scanline rows of 64 rays; 1: tiles in Morton order */
   int32_t tile_w, tile_h;    /* tile shape for ray_order 1, tile_w*tile_h = 64 (0: 8x8) */
   int32_t persistent;        /* 1: persistent launch popping tiles from a device queue */
-  int32_t window_segments;   /* initial depth-window length, in longest segments (0: 2);
+  int32_t window_segments;   /* initial depth-window length, in longest segments (0: 1);
                                 tuning only, never changes results */
   float bg[3];               /* background colour added with the final transmittance */
 } rgx_render_opts;

@@ -341,7 +341,7 @@ static rgx_status make_opts(rgx_context *ctx, const rgx_bvh *b, const rgx_render
   m.persistent = o->persistent ? 1 : 0;
   if (o->window_segments < 0 || o->window_segments > 64)
     return fail(ctx, RGX_ERR_INVALID_ARG, "window_segments must be 0..64");
-  m.window_segments = o->window_segments ? o->window_segments : 2;
+  m.window_segments = o->window_segments ? o->window_segments : 1;
   for (int i = 0; i < 3; i++) m.bg[i] = o->bg[i];
   m.sh_k = b->sh_k;
   m.col_stride = b->col_stride;

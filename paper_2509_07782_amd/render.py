@@ -30,7 +30,7 @@ class RenderOptions:
     tile_w: int = 8
     tile_h: int = 8
     persistent: bool = False
-    window_segments: int = 2
+    window_segments: int = 1
     bg: tuple = (0.0, 0.0, 0.0)
 
 
