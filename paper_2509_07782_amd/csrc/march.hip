@@ -265,16 +265,25 @@ struct SegState {
 
 
 // The N_S sample weights of one Gaussian for one lane:
-// w_k = sigma~ exp(-q(t_k)/2) if q(t_k) <= k^2 else 0.
+// w_k = sigma~ exp(-q(t_k)/2) if q(t_k) <= k^2 else 0.  With t_k = t_0 + k dt
+// and q(t) = A (t - t*)^2 + h^2, the exponent log2 sigma~ - q_k log2(e)/2 is
+// a quadratic in the sample index, e_0 + k e_1 + k^2 e_2, so each sample
+// costs two FMAs before its exp2; the truncation test q_k <= k^2 is the
+// same quadratic against log2 sigma~ - k^2 log2(e)/2.
 template <int NS>
 __device__ __forceinline__ void sample_weights(const Gauss &g, const Chord &c, const Samples &sp,
                                                float *w) {
+  const float u0 = sp.t0 - c.ts;
+  const float Au0 = c.A * u0;
+  const float e0 = fmaf(-fmaf(Au0, u0, c.h2), kHalfLog2e, g.l2sig);
+  const float e1 = -kHalfLog2e * (2.0f * Au0 * sp.dt);
+  const float e2 = -kHalfLog2e * (c.A * sp.dt * sp.dt);
+  const float e_min = fmaf(-g.k2, kHalfLog2e, g.l2sig);
 #pragma unroll
   for (int k = 0; k < NS; k++) {
-    const float u = fmaf((float)k, sp.dt, sp.t0 - c.ts);
-    const float q = fmaf(c.A * u, u, c.h2);
-    const float e = __builtin_amdgcn_exp2f(fmaf(-q, kHalfLog2e, g.l2sig));
-    w[k] = q <= g.k2 ? e : 0.0f;
+    const float x = k == 0 ? e0 : fmaf((float)(k * k), e2, fmaf((float)k, e1, e0));
+    const float e = __builtin_amdgcn_exp2f(x);
+    w[k] = x >= e_min ? e : 0.0f;
   }
 }
 
@@ -1850,16 +1859,19 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
             float wk[NS];
             sample_weights<NS>(g, c, sp, wk);
             // dL/dw_k = dsigma_k + G.c_l T_k phi_k; dq_k = -w_k dL/dw_k / 2
-            float ds = 0.0f, E1 = 0.0f, E2 = 0.0f;
+            // moments over u_k = u_0 + k dt from sums over the sample index
+            float ds = 0.0f, F1 = 0.0f, F2 = 0.0f;
 #pragma unroll
             for (int k = 0; k < NS; k++) {
-              const float u = fmaf((float)k, sp.dt, sp.t0 - c.ts);
               const float wdw = wk[k] * fmaf(GW[k], gc, sg[k]);
               ds += wdw;
-              E1 = fmaf(wdw, u, E1);
-              E2 = fmaf(wdw * u, u, E2);
+              F1 = fmaf((float)k, wdw, F1);
+              F2 = fmaf((float)(k * k), wdw, F2);
               S = fmaf(wk[k], GW[k], S);
             }
+            const float u0 = sp.t0 - c.ts;
+            const float E1 = fmaf(u0, ds, sp.dt * F1);                         // sum wdw u
+            const float E2 = fmaf(u0, fmaf(u0, ds, 2.0f * sp.dt * F1), sp.dt * sp.dt * F2);
             const float D0 = -0.5f * ds, D1 = -0.5f * E1, D2 = -0.5f * E2;
             // z_k = p + u_k d' with p = o' + t* d' (closest approach, local frame)
             const float pxl = fmaf(c.ts, dpx, opx), pyl = fmaf(c.ts, dpy, opy),
