@@ -1206,10 +1206,13 @@ enum CandMode { CAND_ALL = 0, CAND_MARK = 1, CAND_FILTER = 2 };
 // CAND_MARK: fn returns whether some lane hit the candidate, and the entry's
 // mark is set to that; CAND_FILTER: only marked entries are visited (list
 // source only; the brute-force source visits everything).
+// With use_marks, a CAND_MARK pass trusts the marks already set (from a
+// record of the same pass) and visits only the marked entries.
 template <int MODE = CAND_ALL, class Fn>
 __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, WaveMem &M,
                                                    int count, int lane, float a_min, float b_max,
-                                                   int n_active, const Ray &r, Fn &&fn) {
+                                                   int n_active, const Ray &r, Fn &&fn,
+                                                   bool use_marks = false) {
   const float ox = r.ox, oy = r.oy, oz = r.oz;
   if (kind == SRC_LIST) {
     for (int base = 0; base < count; base += 64) {
@@ -1220,7 +1223,8 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
         const int om = M.order[e];
         o = om & (kOrderMark - 1);
         keep = !(M.l_tin[o] > b_max) && !(M.l_tout[o] < a_min);
-        if (MODE == CAND_FILTER) keep = keep && (om & kOrderMark) != 0;
+        if (MODE == CAND_FILTER || (MODE == CAND_MARK && use_marks))
+          keep = keep && (om & kOrderMark) != 0;
         id = M.l_id[o];
       }
       const uint64_t bits0 = ballot(keep);
@@ -1236,7 +1240,7 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
           fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src));
         }
       }
-      if (MODE == CAND_MARK && keep) M.order[e] = o | (hit_mine ? kOrderMark : 0);
+      if (MODE == CAND_MARK && !use_marks && keep) M.order[e] = o | (hit_mine ? kOrderMark : 0);
     }
   } else {
     for (int e = 0; e < n_active; e++) fn(e, with_origin(load_gauss(s.geom, e), ox, oy, oz));
@@ -1244,13 +1248,15 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
 }
 
 // Window-list record of a tile (layout next to kWrecHeader): a forward
-// appends every collection's sorted chunk and the collection state its
-// callers read; a backward of the same rays reads them back in the same
-// order instead of walking the tree.
+// appends every collection's sorted chunk with the collection state its
+// callers read, and after every pass over a list the marks of the entries
+// some lane hit; a backward of the same rays reads them back in the same
+// order instead of walking the tree, and visits only the marked entries.
+// Every record starts with the offset of the tile's next record.
 struct WinRec {
-  uint32_t *slot = nullptr;   // the tile's (complete, first chunk) pair
-  uint32_t cur = kWrecNone;   // replay: next chunk to read; record: last chunk written
-  uint32_t first = kWrecNone; // record: first chunk
+  uint32_t *slot = nullptr;   // the tile's (complete, first record) pair
+  uint32_t cur = kWrecNone;   // replay: next record to read; record: last record written
+  uint32_t first = kWrecNone; // record: first record
   bool ok = false;            // record: nothing dropped so far; replay: tile complete
 };
 
@@ -1268,7 +1274,7 @@ __device__ __forceinline__ void rec_start(WinRec &R, const MarchOpts &op, const 
   }
 }
 
-// forward: the tile's status once all its collections are in
+// forward: the tile's status once all its records are in
 __device__ __forceinline__ void rec_finish(WinRec &R, const MarchOpts &op, int lane) {
   if (op.replay_mode != 1) return;
   if (lane == 0) {
@@ -1277,20 +1283,38 @@ __device__ __forceinline__ void rec_finish(WinRec &R, const MarchOpts &op, int l
   }
 }
 
+// Appends a record of `size` dwords to the tile's chain; kWrecNone (and the
+// tile marked incomplete) when the pool is full.
+__device__ __forceinline__ uint32_t rec_alloc(WinRec &R, const MarchOpts &op, uint32_t size,
+                                              int lane) {
+  uint32_t off = 0;
+  if (lane == 0) off = atomicAdd(op.wrec, size);
+  off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
+  if ((uint64_t)off + size > op.wrec_cap) { R.ok = false; return kWrecNone; }
+  if (lane == 0) {
+    op.wrec[off] = kWrecNone;
+    if (R.cur != kWrecNone) op.wrec[R.cur] = off;   // link from the previous record
+  }
+  if (R.first == kWrecNone) R.first = off;
+  R.cur = off;
+  return off;
+}
+
+// Checks that a record of at least `size` dwords at `off` lies in the pool.
+__device__ __forceinline__ bool rec_fits(const MarchOpts &op, uint32_t off, uint64_t size) {
+  return off < op.wrec_cap && (uint64_t)off + size <= op.wrec_cap;
+}
+
 __device__ __forceinline__ void rec_put(WinRec &R, const MarchOpts &op, const WaveMem &M,
                                         const Trav &t, int cnt, int lane) {
   if (!R.ok) return;
   const int n = cnt > 0 ? cnt : 0;
-  const uint32_t size = kWrecHeader + 3 * n;
-  uint32_t off = 0;
-  if (lane == 0) off = atomicAdd(op.wrec, size);
-  off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
-  if ((uint64_t)off + size > op.wrec_cap) { R.ok = false; return; }
+  const uint32_t off = rec_alloc(R, op, kWrecHeader + 3 * n, lane);
+  if (off == kWrecNone) return;
   uint32_t *p = op.wrec + off;
   if (lane == 0) {
-    p[0] = (uint32_t)cnt; p[1] = t.paused ? 1u : 0u; p[2] = (uint32_t)t.z0;
-    p[3] = (uint32_t)t.z1; p[4] = (uint32_t)t.zp; p[5] = (uint32_t)t.count; p[6] = kWrecNone;
-    if (R.cur != kWrecNone) op.wrec[R.cur + 6] = off;   // link from the tile's previous chunk
+    p[1] = (uint32_t)cnt; p[2] = t.paused ? 1u : 0u; p[3] = (uint32_t)t.z0;
+    p[4] = (uint32_t)t.z1; p[5] = (uint32_t)t.zp; p[6] = (uint32_t)t.count;
   }
   for (int e = lane; e < n; e += 64) {
     const int o = M.order[e] & (kOrderMark - 1);
@@ -1298,20 +1322,38 @@ __device__ __forceinline__ void rec_put(WinRec &R, const MarchOpts &op, const Wa
     p[kWrecHeader + 3 * e + 1] = __float_as_uint(M.l_tin[o]);
     p[kWrecHeader + 3 * e + 2] = __float_as_uint(M.l_tout[o]);
   }
-  if (R.first == kWrecNone) R.first = off;
-  R.cur = off;
 }
 
-// Loads the chunk at pool offset `off` into the list (identity order);
-// returns its collection's result and the tile's next chunk in *next.
+// The marks of the current list's `count` entries after a pass: [next, count,
+// then one 64-bit ballot per 64 entries].
+__device__ __forceinline__ void rec_put_marks(WinRec &R, const MarchOpts &op, const WaveMem &M,
+                                              int count, int lane) {
+  if (!R.ok) return;
+  const int words = (count + 63) >> 6;
+  const uint32_t off = rec_alloc(R, op, 2 + 2 * words, lane);
+  if (off == kWrecNone) return;
+  uint32_t *p = op.wrec + off;
+  if (lane == 0) p[1] = (uint32_t)count;
+  for (int q = 0; q < words; q++) {
+    const int e = 64 * q + lane;
+    const uint64_t b = ballot(e < count && (M.order[e] & kOrderMark) != 0);
+    if (lane == 0) {
+      p[2 + 2 * q] = (uint32_t)b;
+      p[3 + 2 * q] = (uint32_t)(b >> 32);
+    }
+  }
+}
+
+// Loads the chunk at pool offset `off` into the list (identity order, no
+// marks); returns its collection's result and the next record in *next.
 __device__ __forceinline__ int rec_load(const MarchOpts &op, WaveMem &M, uint32_t off, int lane,
                                         uint32_t *next) {
   // a record always fits the pool and the list; anything else is reported
-  if (off >= op.wrec_cap || op.wrec_cap - off < (uint32_t)kWrecHeader) { *next = kWrecNone; return -1; }
+  if (!rec_fits(op, off, kWrecHeader)) { *next = kWrecNone; return -1; }
   const uint32_t *p = op.wrec + off;
-  const int cnt = uniform_int((int)p[0]);
+  const int cnt = uniform_int((int)p[1]);
   const int n = cnt > 0 ? cnt : 0;
-  if (n > kListCap || (uint64_t)off + kWrecHeader + 3 * (uint64_t)n > op.wrec_cap) {
+  if (n > kListCap || !rec_fits(op, off, kWrecHeader + 3 * (uint64_t)n)) {
     *next = kWrecNone;
     return -1;
   }
@@ -1323,8 +1365,47 @@ __device__ __forceinline__ int rec_load(const MarchOpts &op, WaveMem &M, uint32_
     M.order[e] = e;
   }
   __builtin_amdgcn_wave_barrier();
-  *next = (uint32_t)uniform_int((int)p[6]);
+  *next = (uint32_t)uniform_int((int)p[0]);
   return cnt;
+}
+
+// Sets the list's marks from the marks record at `off` (which must cover
+// `count` entries); false on a broken record.
+__device__ __forceinline__ bool rec_load_marks(const MarchOpts &op, WaveMem &M, uint32_t off,
+                                               int count, int lane, uint32_t *next) {
+  const int words = (count + 63) >> 6;
+  if (!rec_fits(op, off, 2 + 2 * (uint64_t)words)) { *next = kWrecNone; return false; }
+  const uint32_t *p = op.wrec + off;
+  if (uniform_int((int)p[1]) != count) { *next = kWrecNone; return false; }
+  __builtin_amdgcn_wave_barrier();
+  for (int q = 0; q < words; q++) {
+    const int e = 64 * q + lane;
+    const uint32_t w = p[2 + 2 * q + (lane >> 5)];
+    if (e < count) {
+      const int o = M.order[e] & (kOrderMark - 1);
+      M.order[e] = o | (((w >> (lane & 31)) & 1u) ? kOrderMark : 0);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  *next = (uint32_t)uniform_int((int)p[0]);
+  return true;
+}
+
+// Backward pass over the current list: in a replayed tile, the forward's
+// marks of this pass (true: visit only those), else false (mark as it goes).
+__device__ __forceinline__ bool rec_next_marks(WinRec &R, const MarchOpts &op, WaveMem &M,
+                                               int count, int kind, int lane, int32_t *err) {
+  if (!(op.replay_mode == 2 && R.ok) || kind != SRC_LIST) return false;
+  uint32_t next;
+  if (R.cur == kWrecNone || !rec_load_marks(op, M, R.cur, count, lane, &next)) {
+    // a broken record (cannot happen): flag it; later reads of this tile's
+    // record find no next record and end its rays
+    if (err) *err = 5;
+    R.cur = kWrecNone;
+    return false;
+  }
+  R.cur = next;
+  return true;
 }
 
 // One collection: the tree walk (recorded in a recording forward) or, in a
@@ -1335,19 +1416,18 @@ __device__ __forceinline__ int collect(const SceneDev &s, const MarchOpts &op, W
                                        int32_t *err, int32_t &nodes, int32_t &leaves,
                                        int64_t *cyc_excl, WinRec &R, uint32_t *start) {
   if (op.replay_mode == 2 && R.ok) {
-    if (R.cur == kWrecNone || R.cur >= op.wrec_cap ||
-        op.wrec_cap - R.cur < (uint32_t)kWrecHeader) {   // a broken record: cannot happen
+    if (R.cur == kWrecNone || !rec_fits(op, R.cur, kWrecHeader)) {   // a broken record
       if (err) *err = 5;
       t.count = 0;
       t.paused = false;
       return -1;
     }
     const uint32_t *p = op.wrec + R.cur;
-    t.paused = uniform_int((int)p[1]) != 0;
-    t.z0 = uniform_int((int)p[2]);
-    t.z1 = uniform_int((int)p[3]);
-    t.zp = uniform_int((int)p[4]);
-    t.count = uniform_int((int)p[5]);
+    t.paused = uniform_int((int)p[2]) != 0;
+    t.z0 = uniform_int((int)p[3]);
+    t.z1 = uniform_int((int)p[4]);
+    t.zp = uniform_int((int)p[5]);
+    t.count = uniform_int((int)p[6]);
     *start = R.cur;
     uint32_t next;
     const int cnt = rec_load(op, M, R.cur, lane, &next);
@@ -1579,14 +1659,15 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; W0[k] = W1[k] = W2[k] = 0.0f; }
       int nhit = 0;
 
-      do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
-                            [&](int j, const Gauss &g) {
+      do {
+        for_each_candidate<CAND_MARK>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
+                                      [&](int j, const Gauss &g) {
         const bool want = go;
         if (stats) cnt[ST_CAND]++;
-        if (ballot(want) == 0) return;
+        if (ballot(want) == 0) return false;
         const Chord c = chord(g, r);
         const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
-        if (ballot(hit) == 0) return;
+        if (ballot(hit) == 0) return false;
         if (stats) cnt[ST_CAND_HIT]++;
         if (hit) {
           nhit++;
@@ -1610,7 +1691,11 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
             W2[k] = fmaf(wk[k], cb, W2[k]);
           }
         }
-      }); while ([&] {
+        return true;
+      });
+        // the entries this pass hit, for a replaying backward
+        if (op.replay_mode == 1 && win.kind == SRC_LIST) rec_put_marks(rec, op, M, win.count, lane);
+      } while ([&] {
         if (stats) cyc_t0 = clock64();
         const bool more = next_chunk(s, op, M, r, lane, n_active, go, a, b, win, stats,
                                      ls.error_flag, cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS],
@@ -1787,8 +1872,10 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
       int nhit = 0;
 
       // pass A: the forward's per-sample sums, in the forward's order
-      do for_each_candidate<CAND_MARK>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
-                                       [&](int j, const Gauss &g) {
+      do {
+        const bool use_marks = rec_next_marks(rec, op, M, win.count, win.kind, lane, ls.error_flag);
+        for_each_candidate<CAND_MARK>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
+                                      [&](int j, const Gauss &g) {
         const bool want = go;
         if (ballot(want) == 0) return false;
         const Chord c = chord(g, r);
@@ -1808,7 +1895,8 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
           }
         }
         return true;
-      }); while (next_chunk(s, op, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
+      }, use_marks);
+      } while (next_chunk(s, op, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
                             dummy_nodes, dummy_leaves, dummy_windows, rec));
 
       // per-sample adjoints: dL/dsigma_k (into sg) and T_k phi_k (into GW);
@@ -1903,21 +1991,30 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
           if (++shb.n == 16) sh_batch_flush(shb, sb, in.acc, op.sh_k, lane);
         };
         // the list still holds the whole window, or the segment's last Z
-        // chunk [zlast, end); a chunked segment then collects [0, zlast) again
-        // (pass A marked the entries of that list some lane hit)
+        // chunk [zlast, end), its entries marked by pass A; a chunked segment
+        // then visits [0, zlast): re-read from the record with the forward's
+        // marks when replaying, else collected again
         const int zlast = win.chunked ? win.t.z0 : 0;
-        for_each_candidate<CAND_FILTER>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
-                                        pass_b);
-        if (win.chunked && zlast > 0 && rec.ok) {
-          // replaying: the segment's earlier chunks come from the record
-          for (uint32_t off = win.rec_first; off != win.rec_last && off != kWrecNone;) {
-            uint32_t next;
+        const bool reread = win.chunked && zlast > 0 && rec.ok;
+        uint32_t off = win.rec_first;
+        int n_cur = win.count, kind_cur = win.kind;
+        for (bool cur = true;; cur = false) {
+          if (!cur) {
+            if (!reread || off == win.rec_last || off == kWrecNone) break;
+            uint32_t next, after;
             const int c = rec_load(op, M, off, lane, &next);
-            off = next;
-            for_each_candidate(SRC_LIST, s, M, c > 0 ? c : 0, lane, a_min, b_max, n_active, r,
-                               pass_b);
+            n_cur = c > 0 ? c : 0;
+            kind_cur = SRC_LIST;
+            if (c < 0 || next == kWrecNone || !rec_load_marks(op, M, next, n_cur, lane, &after)) {
+              if (ls.error_flag) *ls.error_flag = 5;
+              break;
+            }
+            off = after;
           }
-        } else if (win.chunked && zlast > 0) {
+          for_each_candidate<CAND_FILTER>(kind_cur, s, M, n_cur, lane, a_min, b_max, n_active, r,
+                                          pass_b);
+        }
+        if (win.chunked && zlast > 0 && !rec.ok) {
           first_chunk(s, M, r, lane, n_active, any, a, b, zlast, win, false, ls.error_flag,
                       dummy_nodes, dummy_leaves, dummy_windows);
           do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, pass_b);
