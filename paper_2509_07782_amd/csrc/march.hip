@@ -349,9 +349,13 @@ __device__ __forceinline__ float wave_min_dpp(float v) {
   return fminf(fminf(rl(0), rl(16)), fminf(rl(32), rl(48)));
 }
 
-template <int H, int CTRL>
-__device__ __forceinline__ void dpp_stage(float *x, int lane) {
-  const bool up = (lane & H) != 0;
+
+// One reduce-scatter stage over DPP partners: of 2H values per lane, the
+// half picked by lane bit BIT is kept and the partner's other half added (the
+// partner must differ from the lane in that bit).
+template <int H, int CTRL, int BIT>
+__device__ __forceinline__ void dpp_stage_bit(float *x, int lane) {
+  const bool up = (lane & BIT) != 0;
 #pragma unroll
   for (int i = 0; i < H; i++) {
     const float keep = up ? x[i + H] : x[i];
@@ -360,16 +364,23 @@ __device__ __forceinline__ void dpp_stage(float *x, int lane) {
   }
 }
 
-// Sum over the wave of 16 per-lane slots: the in-row DPP stages leave lane
-// p of each row the row's total of slot p, two half-wave swaps add the rows.
-// Lane L returns the wave total of slot L & 15.
-__device__ __forceinline__ float wave_sum_slots16(float *x, int lane) {
-  dpp_stage<8, 0x140>(x, lane);   // row_mirror: lane p <-> 15 - p
-  dpp_stage<4, 0x141>(x, lane);   // row_half_mirror: p <-> 7 - p within 8
-  dpp_stage<2, 0x4e>(x, lane);    // quad_perm [2,3,0,1]
-  dpp_stage<1, 0xb1>(x, lane);    // quad_perm [1,0,3,2]
-  const float y = swap32_sum(x[0], x[0]);
-  return swap16_sum(y, y);
+// Sum over the wave of 16 per-lane slots.  Two half-wave swaps halve the
+// slots per lane (lane bits 5 and 4 pick the half kept), two in-row DPP
+// stages halve them again (bits 3 and 2, with the row and half-row mirrors
+// as partners), and a quad sum completes the total.  Lane L returns the wave
+// total of slot (L >> 2) & 15.
+__device__ __forceinline__ float wave_sum_slots16(const float *g, int lane) {
+  float y[8], z[4];
+#pragma unroll
+  for (int i = 0; i < 8; i++) y[i] = swap32_sum(g[i], g[i + 8]);
+#pragma unroll
+  for (int i = 0; i < 4; i++) z[i] = swap16_sum(y[i], y[i + 4]);
+  dpp_stage_bit<2, 0x140, 8>(z, lane);   // row_mirror: lane p <-> 15 - p
+  dpp_stage_bit<1, 0x141, 4>(z, lane);   // row_half_mirror: p <-> 7 - p within 8
+  float u = z[0];
+  u += dpp<0xb1>(u);                     // quad_perm [1,0,3,2]
+  u += dpp<0x4e>(u);                     // quad_perm [2,3,0,1]
+  return u;
 }
 
 // SH-coefficient gradients of a batch of up to 16 Gaussians as a matrix
@@ -1987,7 +1998,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
           sb[shb.n * kSbStride + lane] = S;
           shb.id = lane == shb.n ? j : shb.id;
           const float mine = wave_sum_slots16(v, lane);
-          if (lane < 16) unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + lane, mine);
+          if ((lane & 3) == 0) unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + (lane >> 2), mine);
           if (++shb.n == 16) sh_batch_flush(shb, sb, in.acc, op.sh_k, lane);
         };
         // the list still holds the whole window, or the segment's last Z
