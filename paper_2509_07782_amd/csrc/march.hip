@@ -203,9 +203,17 @@ __device__ __forceinline__ Pixel tile_pixel(const ViewTable &vt, const MarchOpts
   return p;
 }
 
+// A wave-uniform value held in a vector register: the camera centre is read
+// throughout the march, and scalar registers are the scarcer resource there.
+__device__ __forceinline__ float in_vgpr(float x) {
+  float y;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "s"(x));
+  return y;
+}
+
 __device__ __forceinline__ Ray make_ray(const View &V, int px, int py) {
   Ray r;
-  r.ox = V.c2w[3]; r.oy = V.c2w[7]; r.oz = V.c2w[11];
+  r.ox = in_vgpr(V.c2w[3]); r.oy = in_vgpr(V.c2w[7]); r.oz = in_vgpr(V.c2w[11]);
   const float u = ((float)px + 0.5f - V.cx) / V.fx;
   const float v = ((float)py + 0.5f - V.cy) / V.fy;
   float dx = fmaf(V.c2w[0], u, fmaf(V.c2w[1], v, V.c2w[2]));
@@ -1952,11 +1960,21 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
 #pragma unroll
           for (int e2 = 0; e2 < 16; e2++) v[e2] = 0.0f;
           if (hit) {
+            // everything that needs the geometry record first, so that its
+            // (uniform) registers are free again before the colour record
+            // is loaded
+            float wk[NS];
+            sample_weights<NS>(g, c, sp, wk);
+            // closest-approach point in the local frame, and its world
+            // offset from the mean
+            const float pxl = fmaf(c.ts, dpx, opx), pyl = fmaf(c.ts, dpy, opy),
+                        pzl = fmaf(c.ts, dpz, opz);
+            const float Ps[3] = {fmaf(c.ts, r.dx, r.ox - g.mx), fmaf(c.ts, r.dy, r.oy - g.my),
+                                 fmaf(c.ts, r.dz, r.oz - g.mz)};
+            const float inv_sig = __builtin_amdgcn_rcpf(g.sig);
             float cr, cg, cb;
             colour(s.col, j, Y, cr, cg, cb);
             const float gc = fmaf(Gc0, cr, fmaf(Gc1, cg, Gc2 * cb));
-            float wk[NS];
-            sample_weights<NS>(g, c, sp, wk);
             // dL/dw_k = dsigma_k + G.c_l T_k phi_k; dq_k = -w_k dL/dw_k / 2
             // moments over u_k = u_0 + k dt from sums over the sample index
             float ds = 0.0f, F1 = 0.0f, F2 = 0.0f;
@@ -1973,15 +1991,10 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
             const float E2 = fmaf(u0, fmaf(u0, ds, 2.0f * sp.dt * F1), sp.dt * sp.dt * F2);
             const float D0 = -0.5f * ds, D1 = -0.5f * E1, D2 = -0.5f * E2;
             // z_k = p + u_k d' with p = o' + t* d' (closest approach, local frame)
-            const float pxl = fmaf(c.ts, dpx, opx), pyl = fmaf(c.ts, dpy, opy),
-                        pzl = fmaf(c.ts, dpz, opz);
             const float Zs[3] = {fmaf(D0, pxl, D1 * dpx), fmaf(D0, pyl, D1 * dpy),
                                  fmaf(D0, pzl, D1 * dpz)};
             const float Us[3] = {fmaf(D1, pxl, D2 * dpx), fmaf(D1, pyl, D2 * dpy),
                                  fmaf(D1, pzl, D2 * dpz)};
-            // world offset of the closest-approach point from the mean
-            const float Ps[3] = {fmaf(c.ts, r.dx, r.ox - g.mx), fmaf(c.ts, r.dy, r.oy - g.my),
-                                 fmaf(c.ts, r.dz, r.oz - g.mz)};
             const float dd[3] = {r.dx, r.dy, r.dz};
             v[0] = Zs[0]; v[1] = Zs[1]; v[2] = Zs[2];
 #pragma unroll
@@ -1991,7 +2004,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
             v[12] = fmaf(D0, pxl * pxl, fmaf(2.0f * D1, pxl * dpx, D2 * dpx * dpx));
             v[13] = fmaf(D0, pyl * pyl, fmaf(2.0f * D1, pyl * dpy, D2 * dpy * dpy));
             v[14] = fmaf(D0, pzl * pzl, fmaf(2.0f * D1, pzl * dpz, D2 * dpz * dpz));
-            v[15] = ds * __builtin_amdgcn_rcpf(g.sig);
+            v[15] = ds * inv_sig;
           }
           // slots [0,16): geometry and density, summed over the wave; the SH
           // slots go through the matrix-core batch
