@@ -521,7 +521,7 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
   int64_t tiles = 0;
   for (const ViewTable &t : tabs) tiles += t.n_tiles;
   const size_t need = (size_t)total_rays(cams, n_views) * kReplayK * sizeof(float);
-  const size_t pool = std::min<size_t>(1 + (size_t)tiles * kWrecDwordsPerTile, 0xfffffff0u);
+  const size_t pool = std::min<size_t>(2 + (size_t)tiles * kWrecDwordsPerTile, 0xfffffff0u);
   if (m.ess && !m.brute_force && grow_record(ctx, ctx->replay, need) &&
       grow_record(ctx, ctx->wrec, pool * sizeof(uint32_t)) &&
       grow_record(ctx, ctx->wrec_tile, (size_t)tiles * 2 * sizeof(uint32_t))) {
@@ -530,9 +530,10 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
     m.wrec = (uint32_t *)ctx->wrec.p;
     m.wrec_tile = (uint32_t *)ctx->wrec_tile.p;
     m.wrec_cap = (uint32_t)pool;
-    // the pool's allocation counter starts past itself (a fill kernel, not a
-    // memset node, so the call can be captured)
-    HIP_TRY(ctx, launch_fill(ctx->wrec.p, 1, 1u, stream));
+    // the pool's 64-bit allocation counter (dwords 0-1) starts past itself
+    // (fill kernels, not memset nodes, so the call can be captured)
+    HIP_TRY(ctx, launch_fill(ctx->wrec.p, 1, 2u, stream));
+    HIP_TRY(ctx, launch_fill((uint32_t *)ctx->wrec.p + 1, 1, 0u, stream));
   }
   for (const ViewTable &t : tabs) {
     if (t.n_tiles == 0) continue;

@@ -65,7 +65,7 @@ struct MarchOpts {
   // closest-hit results, a backward of the same rays replays them
   int32_t replay_mode;    // 0 off, 1 record, 2 replay
   float *replay;          // [rays of the call][kReplayK]
-  uint32_t *wrec;         // window-list record pool: [0] allocation counter, chunks after
+  uint32_t *wrec;         // window-list record pool: [0,2) 64-bit allocation counter, records after
   uint32_t *wrec_tile;    // per tile of the call: (complete, first chunk offset)
   uint32_t wrec_cap;      // pool size in dwords
 };

@@ -1306,10 +1306,14 @@ __device__ __forceinline__ void rec_finish(WinRec &R, const MarchOpts &op, int l
 // tile marked incomplete) when the pool is full.
 __device__ __forceinline__ uint32_t rec_alloc(WinRec &R, const MarchOpts &op, uint32_t size,
                                               int lane) {
-  uint32_t off = 0;
-  if (lane == 0) off = atomicAdd(op.wrec, size);
-  off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
-  if ((uint64_t)off + size > op.wrec_cap) { R.ok = false; return kWrecNone; }
+  // a 64-bit allocation counter (pool dwords 0-1): failed allocations keep
+  // adding to it, and it must not wrap back into the pool
+  unsigned long long got = 0;
+  if (lane == 0) got = atomicAdd(reinterpret_cast<unsigned long long *>(op.wrec), (unsigned long long)size);
+  const uint64_t at = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(got >> 32)) << 32) |
+                      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
+  if (at + size > op.wrec_cap) { R.ok = false; return kWrecNone; }
+  const uint32_t off = (uint32_t)at;
   if (lane == 0) {
     op.wrec[off] = kWrecNone;
     if (R.cur != kWrecNone) op.wrec[R.cur] = off;   // link from the previous record
