@@ -278,21 +278,37 @@ struct SegState {
 // a quadratic in the sample index, e_0 + k e_1 + k^2 e_2, so each sample
 // costs two FMAs before its exp2; the truncation test q_k <= k^2 is the
 // same quadratic against log2 sigma~ - k^2 log2(e)/2.
-template <int NS>
-__device__ __forceinline__ void sample_weights(const Gauss &g, const Chord &c, const Samples &sp,
-                                               float *w) {
+// With SKIP, returns the (wave-uniform) mask of samples that some active
+// lane sees inside the Gaussian: the others have w_k = 0 in every lane, and
+// callers may skip them (adding their zero terms would change nothing).  The
+// forward gains from it; in the backward the extra branches cost more
+// registers than they save.
+template <int NS, bool SKIP = false>
+__device__ __forceinline__ uint32_t sample_weights(const Gauss &g, const Chord &c,
+                                                   const Samples &sp, float *w) {
   const float u0 = sp.t0 - c.ts;
   const float Au0 = c.A * u0;
   const float e0 = fmaf(-fmaf(Au0, u0, c.h2), kHalfLog2e, g.l2sig);
   const float e1 = -kHalfLog2e * (2.0f * Au0 * sp.dt);
   const float e2 = -kHalfLog2e * (c.A * sp.dt * sp.dt);
   const float e_min = fmaf(-g.k2, kHalfLog2e, g.l2sig);
+  uint32_t live = 0;
 #pragma unroll
   for (int k = 0; k < NS; k++) {
     const float x = k == 0 ? e0 : fmaf((float)(k * k), e2, fmaf((float)k, e1, e0));
-    const float e = __builtin_amdgcn_exp2f(x);
-    w[k] = x >= e_min ? e : 0.0f;
+    const bool in = x >= e_min;
+    if (SKIP) {
+      w[k] = 0.0f;
+      if (ballot(in) != 0) {
+        w[k] = in ? __builtin_amdgcn_exp2f(x) : 0.0f;
+        live |= 1u << k;
+      }
+    } else {
+      const float e = __builtin_amdgcn_exp2f(x);
+      w[k] = in ? e : 0.0f;
+    }
   }
+  return SKIP ? live : (1u << NS) - 1u;
 }
 
 // Segment bounds [a, b], step and sample positions of a live lane.
@@ -1705,9 +1721,10 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
           float cr, cg, cb;
           colour(s.col, j, Y, cr, cg, cb);
           float wk[NS];
-          sample_weights<NS>(g, c, sp, wk);
+          const uint32_t live = sample_weights<NS, true>(g, c, sp, wk);
 #pragma unroll
           for (int k = 0; k < NS; k++) {
+            if (!(live & (1u << k))) continue;
             sg[k] += wk[k];
             W0[k] = fmaf(wk[k], cr, W0[k]);
             W1[k] = fmaf(wk[k], cg, W1[k]);
