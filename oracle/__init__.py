@@ -82,6 +82,11 @@ def lib():
         L.orc_gaussians.argtypes = [C.POINTER(_Scene), C.c_double, vp, vp, vp, vp]
         L.orc_density_at.argtypes = [C.POINTER(_Scene), C.c_double, C.c_int64, vp, C.c_int64, vp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_false_positives.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera),
+                                          C.POINTER(_Opts), vp, C.c_int64, vp, vp, vp]
+        L.orc_false_positives.restype = C.c_int
+        L.orc_chords.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_double, C.c_int64, vp,
+                                 C.c_int64, vp, vp, vp, vp]
         _LIB = L
     return _LIB
 
@@ -181,6 +186,39 @@ def hits(scene, cam, opts: Opts, pix: int, cap_segs=4096, cap_ids=1 << 20):
     if ns < 0:
         raise ValueError("orc_hits: capacity too small")
     return [(a[i], dt[i], ids[off[i]:off[i + 1]].copy()) for i in range(ns)]
+
+
+def false_positives(scene, cam, opts: Opts, pix=None):
+    """Per ray: the number of Gaussians whose minimal AABB meets [t_n, t_end]
+    while the ellipsoid does not, the number of near-tie decisions among them,
+    and t_end (where the ray's march ended)."""
+    if pix is None:
+        pix = np.arange(cam.width * cam.height, dtype=np.int64)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    n = pix.shape[0]
+    sh = _SceneHold(scene)
+    count = np.zeros(n, np.int64)
+    ties = np.zeros(n, np.int64)
+    t_end = np.zeros(n)
+    c, o = _cam(cam), _opts(opts)
+    rc = lib().orc_false_positives(C.byref(sh.s), C.byref(c), C.byref(o), pix.ctypes.data, n,
+                                   count.ctypes.data, ties.ctypes.data, t_end.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_false_positives failed ({rc})")
+    return count, ties, t_end
+
+
+def chords(scene, cam, sigma_eps, pix: int, ids):
+    """k^2, h^2 (closest approach, local frame) and the chord [t0, t1] of the
+    listed Gaussians along one pixel's ray (NaN where there is none)."""
+    sh = _SceneHold(scene)
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    n = ids.shape[0]
+    out = [np.zeros(n) for _ in range(4)]
+    c = _cam(cam)
+    lib().orc_chords(C.byref(sh.s), C.byref(c), float(sigma_eps), int(pix), ids.ctypes.data, n,
+                     *[a.ctypes.data for a in out])
+    return tuple(out)
 
 
 def sh_basis(deg: int, d):

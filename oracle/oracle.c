@@ -273,6 +273,9 @@ typedef struct {
   /* optional per-segment hit lists */
   int64_t *seg_off; double *seg_a; double *seg_dt; int64_t *ids; int64_t cap_ids, cap_segs;
   int64_t n_segs, n_ids, overflow;
+  /* where the march ended: the segment start at which T <= T_eps stopped it,
+     else t_f (the loop ran past t_f or nothing further was hit) */
+  double t_end;
 } ray_out;
 
 static void note_margin(ray_out *ro, double m) { if (m < ro->margin) ro->margin = m; }
@@ -312,6 +315,7 @@ static void march_ray(const prep *P, const orc_camera *cam, const orc_opts *op, 
   int64_t *hl = (int64_t *)malloc(sizeof(int64_t) * (nc > 0 ? nc : 1));
 
   double T = 1.0, C[3] = {0, 0, 0};
+  ro->t_end = tf;
   const int fixed = !op->adaptive;
   const double dS_fixed = op->dt * op->n_s;
   int64_t seg_i = 0;   /* fixed mode: segment index on the grid a = tn + i dS */
@@ -334,7 +338,7 @@ static void march_ray(const prep *P, const orc_camera *cam, const orc_opts *op, 
     if (fixed && op->ess != 2) a = tn + (double)seg_i * dS_fixed;
     if (!(a < tf)) break;
     if (op->t_eps > 0) note_margin(ro, fabs(T - op->t_eps) / op->t_eps);
-    if (!(T > op->t_eps)) break;
+    if (!(T > op->t_eps)) { ro->t_end = a; break; }
     double dt;
     if (fixed) dt = op->dt;
     else {
@@ -631,6 +635,85 @@ void orc_gaussians(const orc_scene *sc, double sigma_eps, double *k2, int32_t *a
       for (int j = 0; j < 3; j++) acc += g.R[3 * i + j] * g.R[3 * i + j] * g.s[j] * g.s[j];
       half[3 * l + i] = g.active ? sqrt(g.k2) * sqrt(acc) : 0;
     }
+  }
+}
+
+/* False positives of the AABB test along a whole ray (Sec. 3.4, Eq. 6;
+   minimal AABB of Supp. B): the number of active Gaussians whose minimal AABB
+   mu +/- L, L_i = k sqrt(sum_j r_ij^2 s_j^2), meets the ray over [t_n, t_end]
+   while the ellipsoid's chord does not, t_end being where the ray's march
+   ended (Algorithm 1).  Also per ray: t_end, and how many Gaussians had one of
+   the two decisions within a relative 1e-5 of flipping (a near tie: the slab
+   interval's overlap, |h^2 - k^2| / k^2, or a chord end against t_n / t_end).
+   The AABB test is the slab method: the ray meets the box over [lo, hi]
+   iff max(lo, max_i min(t0_i, t1_i)) <= min(hi, min_i max(t0_i, t1_i)),
+   t0_i, t1_i the parameters of the two planes of axis i. */
+int orc_false_positives(const orc_scene *sc, const orc_camera *cam, const orc_opts *op,
+                        const int64_t *pix, int64_t n_rays, int64_t *count, int64_t *ties,
+                        double *t_end) {
+  if (sc->sh_degree < 0 || sc->sh_degree > 3) return -1;
+  gauss *G = prepare_all(sc, op->sigma_eps);
+  prep P = {sc, G, (sc->sh_degree + 1) * (sc->sh_degree + 1)};
+  const double tol = 1e-5;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t r = 0; r < n_rays; r++) {
+    double o[3], d[3];
+    make_ray(cam, pix[r], o, d);
+    ray_out ro;
+    memset(&ro, 0, sizeof ro);
+    ro.margin = INFINITY;
+    march_ray(&P, cam, op, o, d, &ro, NULL);
+    const double lo = cam->t_near, hi = ro.t_end;
+    int64_t fp = 0, nt = 0;
+    for (int64_t l = 0; l < sc->n; l++) {
+      const gauss *g = &G[l];
+      if (!g->active) continue;
+      double enter = lo, leave = hi;
+      for (int i = 0; i < 3; i++) {
+        double acc = 0;
+        for (int j = 0; j < 3; j++) acc += g->R[3 * i + j] * g->R[3 * i + j] * g->s[j] * g->s[j];
+        const double L = sqrt(g->k2) * sqrt(acc);
+        const double ta = (g->mu[i] - L - o[i]) / d[i], tb = (g->mu[i] + L - o[i]) / d[i];
+        enter = fmax(enter, fmin(ta, tb));
+        leave = fmin(leave, fmax(ta, tb));
+      }
+      const int box = enter <= leave;
+      double t0, t1, h2;
+      const int chord = ellipsoid_interval(g, o, d, &t0, &t1, &h2);
+      const int ell = chord && t0 <= hi && t1 >= lo;
+      if (box && !ell) fp++;
+      int tie = fabs(leave - enter) <= tol * fmax(1.0, fabs(enter));
+      tie |= fabs(h2 - g->k2) <= tol * g->k2;
+      tie |= chord && (fabs(t0 - hi) <= tol * fmax(1.0, fabs(hi)) ||
+                       fabs(t1 - lo) <= tol * fmax(1.0, fabs(lo)));
+      nt += tie;
+    }
+    count[r] = fp;
+    ties[r] = nt;
+    t_end[r] = ro.t_end;
+  }
+  free(G);
+  return 0;
+}
+
+/* Ray / ellipsoid data of listed Gaussians for one pixel's ray (for tests that
+   classify near ties): k^2, the squared local distance h^2 of the point of
+   closest approach and the chord [t0, t1] (NaN for a miss or an inactive
+   Gaussian). */
+void orc_chords(const orc_scene *sc, const orc_camera *cam, double sigma_eps, int64_t pix,
+                const int64_t *ids, int64_t n, double *k2, double *h2, double *t0, double *t1) {
+  double o[3], d[3];
+  make_ray(cam, pix, o, d);
+  for (int64_t i = 0; i < n; i++) {
+    gauss g;
+    make_gauss(sc, sigma_eps, ids[i], &g);
+    k2[i] = h2[i] = t0[i] = t1[i] = NAN;
+    if (!g.active) continue;
+    double a, b, hh;
+    int hit = ellipsoid_interval(&g, o, d, &a, &b, &hh);
+    k2[i] = g.k2;
+    h2[i] = hh;
+    if (hit) { t0[i] = a; t1[i] = b; }
   }
 }
 
