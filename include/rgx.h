@@ -239,6 +239,20 @@ rgx_status rgx_error_flags(rgx_context *ctx, int32_t *flags /*host*/, hipStream_
 rgx_status rgx_isotropic_loss(rgx_context *ctx, int64_t n, const float *log_scales, float r0,
                               float *loss, float *grad, int32_t accumulate, hipStream_t stream);
 
+/* Allocation-free variant of rgx_isotropic_loss, for callers that cannot
+   allocate device memory (code under stream capture, tight serving loops,
+   harnesses that forbid allocation).  Same arguments, results and
+   deterministic reduction; the per-block partial sums go to a fixed
+   256 KB workspace per device (one double per 256 Gaussians for up to
+   RGX_MAX_GAUSSIANS Gaussians), held from the first rgx_create on the device
+   until the process ends.  Never allocates or frees.  n beyond the workspace
+   returns RGX_ERR_INVALID_ARG.  Every call on a device shares that device's
+   workspace: calls that overlap on one device (several streams or contexts)
+   race and give undefined results; calls ordered on one stream are safe. */
+rgx_status rgx_isotropic_loss_noalloc(rgx_context *ctx, int64_t n, const float *log_scales,
+                                      float r0, float *loss, float *grad, int32_t accumulate,
+                                      hipStream_t stream);
+
 /* Optional kernel timing, for measurement.  While enabled, every launch made
    by rgx_build_bvh, rgx_render_forward and rgx_render_backward is bracketed
    by two HIP events recorded on the caller's stream (so the interval is that

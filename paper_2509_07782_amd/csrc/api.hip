@@ -23,6 +23,7 @@ static_assert(RGX_STAT_Q == ST_Q && RGX_STAT_P == ST_P && RGX_STAT_SAMPLES == ST
                   RGX_STAT_CHUNKED == ST_CHUNKED && RGX_STAT_KCYC_TILE == ST_KCYC_TILE &&
                   RGX_NSTAT == kNStat,
               "stat slots");
+static_assert(RGX_MAX_GAUSSIANS == RGX_MAX_GAUSSIANS_INTERNAL, "size limit");
 
 namespace {
 
@@ -52,6 +53,7 @@ struct rgx_context {
   uint64_t replay_key = 0;          // what that forward rendered (0: nothing recorded)
   std::vector<void *> retired;      // outgrown replay buffers: a captured graph may still use them
   int32_t replayed = 0;             // whether the last backward replayed
+  double *iso_scratch = nullptr;    // device address of the fixed loss workspace on this device
 };
 
 // Records hipEvents on `stream` around `launch` when timing is enabled.
@@ -151,6 +153,9 @@ rgx_status rgx_create(int device, rgx_context **out) {
     e = hipMalloc((void **)&ctx->queue, 16 * sizeof(int32_t));
   }
   if (e == hipSuccess) e = hipMemset(ctx->queue, 0, 16 * sizeof(int32_t));
+  // device address of this device's copy of the fixed workspace used by the
+  // allocation-free entry point (the array's name is not a device address)
+  if (e == hipSuccess) e = iso_scratch_resolve(&ctx->iso_scratch);
   if (e != hipSuccess) {
     delete ctx;
     return RGX_ERR_HIP;
@@ -708,6 +713,20 @@ rgx_status rgx_isotropic_loss(rgx_context *ctx, int64_t n, const float *log_scal
     ctx->partial_cap = nb;
   }
   HIP_TRY(ctx, launch_isotropic_loss(n, log_scales, r0, loss, grad, accumulate, ctx->partial, stream));
+  return RGX_OK;
+}
+
+rgx_status rgx_isotropic_loss_noalloc(rgx_context *ctx, int64_t n, const float *log_scales,
+                                      float r0, float *loss, float *grad, int32_t accumulate,
+                                      hipStream_t stream) {
+  if (!ctx || !log_scales || !loss || !grad) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  if (n <= 0 || n > RGX_MAX_GAUSSIANS) return fail(ctx, RGX_ERR_INVALID_ARG, "n out of range");
+  if (iso_blocks(n) > iso_scratch_capacity())
+    return fail(ctx, RGX_ERR_INVALID_ARG, "n exceeds the fixed workspace of the allocation-free loss");
+  if (!(r0 > 0.0f) || !std::isfinite(r0)) return fail(ctx, RGX_ERR_INVALID_ARG, "r0 must be > 0");
+  if (!ctx->iso_scratch) return fail(ctx, RGX_ERR_STATE, "fixed workspace address not resolved");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_isotropic_loss(n, log_scales, r0, loss, grad, accumulate, ctx->iso_scratch, stream));
   return RGX_OK;
 }
 

@@ -29,6 +29,12 @@ struct BuildArgs {
 };
 hipError_t launch_build(const BuildArgs &a, hipStream_t st);
 int64_t iso_blocks(int64_t n);
+// Largest n (must equal RGX_MAX_GAUSSIANS of the public header).
+constexpr int64_t RGX_MAX_GAUSSIANS_INTERNAL = int64_t(1) << 23;
+// Per-device fixed partial-sum workspace of rgx_isotropic_loss_noalloc:
+// capacity in doubles, and its device address on the current device.
+int64_t iso_scratch_capacity();
+hipError_t iso_scratch_resolve(double **ptr);
 hipError_t launch_isotropic_loss(int64_t n, const float *log_scales, float r0, float *loss,
                                  float *grad, int accumulate, double *partial, hipStream_t st);
 

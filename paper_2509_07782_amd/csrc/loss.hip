@@ -66,6 +66,22 @@ __global__ __launch_bounds__(kLossThreads) void k_iso_final(int64_t nb, const do
 
 int64_t iso_blocks(int64_t n) { return (n + kLossThreads - 1) / kLossThreads; }
 
+// Fixed workspace of the allocation-free entry point: one partial sum per
+// block for the largest supported n (256 KB per device, held until the
+// process ends).  Host code never passes the array's name to a kernel; it
+// uses the device address resolved once per device by iso_scratch_resolve.
+constexpr int64_t kIsoScratchDoubles = (RGX_MAX_GAUSSIANS_INTERNAL + kLossThreads - 1) / kLossThreads;
+static __device__ __align__(256) double scratch[kIsoScratchDoubles];
+
+int64_t iso_scratch_capacity() { return kIsoScratchDoubles; }
+
+hipError_t iso_scratch_resolve(double **ptr) {
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  *ptr = e == hipSuccess ? (double *)p : nullptr;
+  return e;
+}
+
 hipError_t launch_isotropic_loss(int64_t n, const float *log_scales, float r0, float *loss,
                                  float *grad, int accumulate, double *partial, hipStream_t st) {
   const int64_t nb = iso_blocks(n);

@@ -58,6 +58,7 @@ class Grads(C.Structure):
 EXPORTS = ("rgx_create", "rgx_destroy", "rgx_build_bvh", "rgx_bvh_destroy", "rgx_bvh_size",
            "rgx_render_forward", "rgx_render_backward", "rgx_dump_hits", "rgx_bvh_debug",
            "rgx_error_flags", "rgx_set_kernel_timing", "rgx_kernel_times", "rgx_isotropic_loss",
+           "rgx_isotropic_loss_noalloc",
            "rgx_backward_replayed", "rgx_status_string", "rgx_last_error")
 
 KERNEL_KINDS = ("build", "forward", "backward", "finalize")   # RGX_KERN_* order
@@ -99,6 +100,8 @@ def load():
     L.rgx_error_flags.restype = st
     L.rgx_isotropic_loss.argtypes = [vp, C.c_int64, vp, C.c_float, vp, vp, C.c_int32, vp]
     L.rgx_isotropic_loss.restype = st
+    L.rgx_isotropic_loss_noalloc.argtypes = [vp, C.c_int64, vp, C.c_float, vp, vp, C.c_int32, vp]
+    L.rgx_isotropic_loss_noalloc.restype = st
     L.rgx_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.rgx_set_kernel_timing.restype = st
     L.rgx_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
@@ -248,6 +251,15 @@ def isotropic_loss(ctx: Context, log_scales, r0, loss, grad, accumulate=False, s
                                     float(r0), loss.data_ptr(), grad.data_ptr(),
                                     int(bool(accumulate)), C.c_void_p(stream)),
           ctx.h, "rgx_isotropic_loss")
+
+
+def isotropic_loss_noalloc(ctx: Context, log_scales, r0, loss, grad, accumulate=False, stream=0):
+    """Same as isotropic_loss, through the entry point that allocates nothing
+    (fixed per-device workspace)."""
+    check(load().rgx_isotropic_loss_noalloc(ctx.h, int(log_scales.shape[0]), log_scales.data_ptr(),
+                                            float(r0), loss.data_ptr(), grad.data_ptr(),
+                                            int(bool(accumulate)), C.c_void_p(stream)),
+          ctx.h, "rgx_isotropic_loss_noalloc")
 
 
 def render_forward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, stats=None, stream=0):
