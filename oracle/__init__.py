@@ -28,7 +28,8 @@ STAT_NAMES = ("Q", "P", "samples", "segments", "closest")
 class _Scene(C.Structure):
     _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32),
                 ("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("density", C.c_void_p), ("sh", C.c_void_p)]
+                ("density", C.c_void_p), ("sh", C.c_void_p), ("n_sg", C.c_int32),
+                ("sg", C.c_void_p)]
 
 
 class _Camera(C.Structure):
@@ -72,7 +73,8 @@ def lib():
                                  C.c_int64, vp, vp, vp, vp]
         L.orc_render.restype = C.c_int
         L.orc_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Opts), vp,
-                                   C.c_int64, vp, vp, vp, vp, vp, vp, vp]
+                                   C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_colour.argtypes = [C.POINTER(_Scene), C.c_int64, vp, C.c_int64, vp]
         L.orc_backward.restype = C.c_int
         L.orc_hits.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Opts), C.c_int64,
                                vp, vp, vp, C.c_int64, vp, C.c_int64]
@@ -96,12 +98,18 @@ def _f64(a):
 
 
 class _SceneHold:
-    """Keeps float64 copies alive while the C structure points at them."""
+    """Keeps float64 copies alive while the C structure points at them.
+    A scene may carry spherical-Gaussian lobes: "sg" [n, n_sg, 7] (amplitude
+    rgb, axis xyz, sharpness)."""
 
     def __init__(self, scene):
         self.arrs = [_f64(scene[k]) for k in ("means", "log_scales", "quats", "density", "sh")]
         n = self.arrs[0].shape[0]
-        self.s = _Scene(n, int(scene["sh_degree"]), *[a.ctypes.data for a in self.arrs])
+        sg = scene.get("sg")
+        self.sg = None if sg is None or np.size(sg) == 0 else _f64(sg).reshape(n, -1, 7)
+        n_sg = 0 if self.sg is None else self.sg.shape[1]
+        self.s = _Scene(n, int(scene["sh_degree"]), *[a.ctypes.data for a in self.arrs], n_sg,
+                        None if self.sg is None else self.sg.ctypes.data)
 
 
 def _cam(cam) -> _Camera:
@@ -162,12 +170,15 @@ def backward(scene, cam, opts: Opts, pix, grad_rgb, grad_T=None):
     N = sh.arrs[0].shape[0]
     out = dict(means=np.zeros((N, 3)), log_scales=np.zeros((N, 3)), quats=np.zeros((N, 4)),
                density=np.zeros(N), sh=np.zeros(sh.arrs[4].shape))
+    if sh.sg is not None:
+        out["sg"] = np.zeros(sh.sg.shape)
     c, o = _cam(cam), _opts(opts)
     rc = lib().orc_backward(C.byref(sh.s), C.byref(c), C.byref(o), pix.ctypes.data, n,
                             g_rgb.ctypes.data, None if g_T is None else g_T.ctypes.data,
                             out["means"].ctypes.data, out["log_scales"].ctypes.data,
                             out["quats"].ctypes.data, out["density"].ctypes.data,
-                            out["sh"].ctypes.data)
+                            out["sh"].ctypes.data,
+                            out["sg"].ctypes.data if "sg" in out else None)
     if rc != 0:
         raise ValueError(f"orc_backward failed ({rc})")
     return out
@@ -219,6 +230,16 @@ def chords(scene, cam, sigma_eps, pix: int, ids):
     lib().orc_chords(C.byref(sh.s), C.byref(c), float(sigma_eps), int(pix), ids.ctypes.data, n,
                      *[a.ctypes.data for a in out])
     return tuple(out)
+
+
+def colour(scene, l: int, dirs):
+    """Colour [n,3] of Gaussian l at the listed unit directions (SH sum plus
+    spherical-Gaussian lobes)."""
+    sh = _SceneHold(scene)
+    d = _f64(dirs).reshape(-1, 3)
+    out = np.zeros((d.shape[0], 3))
+    lib().orc_colour(C.byref(sh.s), int(l), d.ctypes.data, d.shape[0], out.ctypes.data)
+    return out
 
 
 def sh_basis(deg: int, d):

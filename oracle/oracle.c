@@ -50,6 +50,8 @@ typedef struct {
   const double *quats;      /* [n,4] (w,x,y,z), unnormalised */
   const double *density;    /* [n]   raw sigma~ */
   const double *sh;         /* [n,K,3] */
+  int32_t n_sg;             /* spherical-Gaussian lobes per Gaussian (0 = SH colour only) */
+  const double *sg;         /* [n, n_sg, 7]: amplitude rgb, axis xyz (any norm > 0), sharpness */
 } orc_scene;
 
 typedef struct {
@@ -157,6 +159,53 @@ void orc_sh_basis(int32_t deg, const double d[3], double *Y) {
 
 /* ------------------------------------------------------------------------ */
 /* Rays: pinhole through the pixel centre, unit direction (so t is metric).  */
+
+/* Colour of Gaussian l at the unit direction d: the SH sum (Eq. 1's c_l(d))
+   plus, when the scene has spherical-Gaussian lobes (the 9 SH + 7 SG
+   appearance model of the supplement's comparison), the lobes
+   a_j exp(lambda_j (xi_j.d / |xi_j| - 1)).  Used as is (no offset or clamp).
+   A lobe with a zero axis contributes nothing. */
+static void gaussian_colour(const orc_scene *sc, int K, int64_t l, const double *Y, const double d[3],
+                            double col[3]) {
+  for (int ch = 0; ch < 3; ch++) {
+    double c = 0;
+    for (int m = 0; m < K; m++) c += sc->sh[(l * K + m) * 3 + ch] * Y[m];
+    col[ch] = c;
+  }
+  for (int j = 0; j < sc->n_sg; j++) {
+    const double *p = sc->sg + (l * sc->n_sg + j) * 7;
+    const double xn = sqrt(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
+    if (!(xn > 0)) continue;
+    const double cosang = (p[3] * d[0] + p[4] * d[1] + p[5] * d[2]) / xn;
+    const double g = exp(p[6] * (cosang - 1.0));
+    for (int ch = 0; ch < 3; ch++) col[ch] += p[ch] * g;
+  }
+}
+
+/* Adds dL/d(lobe parameters of Gaussian l) for dL/dc = dc[3] at direction d:
+   da_j = g_j dc, dlambda_j = (a_j.dc) g_j (cos_j - 1), and through the unit
+   axis u_j = xi_j / |xi_j|: dxi_j = (a_j.dc) g_j lambda_j (d - cos_j u_j) / |xi_j|. */
+static void sg_backward(const orc_scene *sc, int64_t l, const double d[3], const double dc[3],
+                        double *g_sg) {
+  for (int j = 0; j < sc->n_sg; j++) {
+    const double *p = sc->sg + (l * sc->n_sg + j) * 7;
+    double *gp = g_sg + (l * sc->n_sg + j) * 7;
+    const double xn = sqrt(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
+    if (!(xn > 0)) continue;
+    const double u[3] = {p[3] / xn, p[4] / xn, p[5] / xn};
+    const double cosang = u[0] * d[0] + u[1] * d[1] + u[2] * d[2];
+    const double g = exp(p[6] * (cosang - 1.0));
+    const double ad = p[0] * dc[0] + p[1] * dc[1] + p[2] * dc[2];
+    double add[7];
+    for (int ch = 0; ch < 3; ch++) add[ch] = g * dc[ch];
+    for (int i = 0; i < 3; i++) add[3 + i] = ad * g * p[6] * (d[i] - cosang * u[i]) / xn;
+    add[6] = ad * g * (cosang - 1.0);
+    for (int i = 0; i < 7; i++) {
+#pragma omp atomic
+      gp[i] += add[i];
+    }
+  }
+}
 
 static void make_ray(const orc_camera *c, int64_t pix, double o[3], double d[3]) {
   int64_t u = pix % c->width, v = pix / c->width;
@@ -305,12 +354,7 @@ static void march_ray(const prep *P, const orc_camera *cam, const orc_opts *op, 
   double Y[16];
   orc_sh_basis(deg, d, Y);
   double *col = (double *)malloc(sizeof(double) * 3 * (nc > 0 ? nc : 1));
-  for (int64_t i = 0; i < nc; i++)
-    for (int ch = 0; ch < 3; ch++) {
-      double c = 0;
-      for (int m = 0; m < K; m++) c += P->sc->sh[(cd[i].id * K + m) * 3 + ch] * Y[m];
-      col[3 * i + ch] = c;
-    }
+  for (int64_t i = 0; i < nc; i++) gaussian_colour(P->sc, K, cd[i].id, Y, d, col + 3 * i);
   unsigned char *seen = (unsigned char *)calloc(nc > 0 ? nc : 1, 1);
   int64_t *hl = (int64_t *)malloc(sizeof(int64_t) * (nc > 0 ? nc : 1));
 
@@ -522,7 +566,9 @@ static void drot_dq(const double q[4], const double dR[9], double dq[4]) {
    be NULL).  Reverse sweep over each ray's recorded samples. */
 int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_opts *op, const int64_t *pix,
                  int64_t n_rays, const double *grad_rgb, const double *grad_T, double *g_means,
-                 double *g_log_scales, double *g_quats, double *g_density, double *g_sh) {
+                 double *g_log_scales, double *g_quats, double *g_density, double *g_sh,
+                 double *g_sg) {
+  if (sc->n_sg < 0 || (sc->n_sg > 0 && (!sc->sg || !g_sg))) return -1;
   if (sc->sh_degree < 0 || sc->sh_degree > 3) return -1;
   gauss *G = prepare_all(sc, op->sigma_eps);
   const int K = (sc->sh_degree + 1) * (sc->sh_degree + 1);
@@ -569,10 +615,7 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_opts *op,
         const gauss *g = &G[cb->g];
         const int64_t l = cb->g;
         double col[3];
-        for (int ch = 0; ch < 3; ch++) {
-          col[ch] = 0;
-          for (int m = 0; m < K; m++) col[ch] += sc->sh[(l * K + m) * 3 + ch] * Y[m];
-        }
+        gaussian_colour(sc, K, l, Y, d, col);
         double dw = dsig + dW[0] * col[0] + dW[1] * col[1] + dW[2] * col[2];
         double dq = -0.5 * cb->w * dw; /* w = sig exp(-q/2) */
         double xm[3] = {o[0] + s->t * d[0] - g->mu[0], o[1] + s->t * d[1] - g->mu[1],
@@ -608,6 +651,10 @@ int orc_backward(const orc_scene *sc, const orc_camera *cam, const orc_opts *op,
 #pragma omp atomic
             g_sh[(l * K + m) * 3 + ch] += Y[m] * cb->w * dW[ch];
           }
+        if (sc->n_sg) {
+          const double dc[3] = {cb->w * dW[0], cb->w * dW[1], cb->w * dW[2]};
+          sg_backward(sc, l, d, dc, g_sg);
+        }
       }
       for (int ch = 0; ch < 3; ch++) S[ch] += Tk[k] * phi * s->W[ch];
     }
@@ -714,6 +761,16 @@ void orc_chords(const orc_scene *sc, const orc_camera *cam, double sigma_eps, in
     k2[i] = g.k2;
     h2[i] = hh;
     if (hit) { t0[i] = a; t1[i] = b; }
+  }
+}
+
+/* Colour of Gaussian l at listed unit directions (for tests of the colour model). */
+void orc_colour(const orc_scene *sc, int64_t l, const double *dirs, int64_t n, double *out) {
+  const int K = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+  for (int64_t i = 0; i < n; i++) {
+    double Y[16];
+    orc_sh_basis(sc->sh_degree, dirs + 3 * i, Y);
+    gaussian_colour(sc, K, l, Y, dirs + 3 * i, out + 3 * i);
   }
 }
 

@@ -114,11 +114,15 @@ def _shell_means(rng, n, r_lo=2.0, r_hi=50.0):
 
 
 def make_scene(kind: str, n: int, seed: int, sh_degree: int | None = None,
-               log_scale_sd: float = 0.5) -> dict:
+               log_scale_sd: float = 0.5, n_sg: int = 0) -> dict:
     """Draw a scene of `n` Gaussians.
 
     kind: "uniform" (config 1), "cluster" (configs 2-3) or "outdoor"
     (configs 4-5).  Returns float32 arrays as described in the module doc.
+    n_sg > 0 adds spherical-Gaussian colour lobes "sg" [n, n_sg, 7]:
+    amplitudes N(0, 0.2) per channel, axes uniform on the sphere times a
+    length U(0.5, 2), sharpness U(1, 30); drawn after everything else, so
+    the other arrays do not depend on n_sg.
     """
     rng = np.random.default_rng(seed)
     if kind == "uniform":
@@ -147,8 +151,15 @@ def make_scene(kind: str, n: int, seed: int, sh_degree: int | None = None,
         sh = colour / SH_C0
     else:
         sh = rng.normal(0.0, 0.2, (n, k, 3))
-    return dict(means=means.astype(np.float32), log_scales=log_scales.astype(np.float32),
-                quats=quats, density=density, sh=sh.astype(np.float32), sh_degree=deg)
+    out = dict(means=means.astype(np.float32), log_scales=log_scales.astype(np.float32),
+               quats=quats, density=density, sh=sh.astype(np.float32), sh_degree=deg)
+    if n_sg:
+        amp = rng.normal(0.0, 0.2, (n, n_sg, 3))
+        ax = rng.standard_normal((n, n_sg, 3))
+        ax *= (rng.uniform(0.5, 2.0, (n, n_sg, 1)) / np.linalg.norm(ax, axis=2, keepdims=True))
+        lam = rng.uniform(1.0, 30.0, (n, n_sg, 1))
+        out["sg"] = np.concatenate([amp, ax, lam], axis=2).astype(np.float32)
+    return out
 
 
 def subset_scene(scene: dict, idx) -> dict:
