@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--workload", type=int, default=3,
                     help="3: 1M-Gaussian training step (default); 5: 5M Gaussians, 16 mixed "
                          "views, persistent + graph-captured step vs 16 plain launches")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the bounded side measurements of the other workloads")
+    ap.add_argument("--side-reps", type=int, default=3)
     return ap.parse_args()
 
 
@@ -131,7 +134,7 @@ def main():
         loss = step()
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    log(f"timed {args.steps} steps: {t_total:.3f}s, loss {float(loss):.5f}")
+    log(f"timed {args.steps} steps: {t_total:.3f}s, loss {float(loss.detach()):.5f}")
     ms_step = 1000.0 * t_total / args.steps
     kt = renderer.ctx.kernel_times()
     renderer.ctx.set_kernel_timing(False)
@@ -211,6 +214,12 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": dom_bytes},
     }
+    if not args.no_side:
+        # free the headline workload's buffers before the larger scenes
+        del params, target
+        renderer.close()
+        torch.cuda.empty_cache()
+        out["side"] = side_measurements(args.side_reps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cams, opts, args.cpu_stride)
     line = json.dumps(out)
@@ -280,6 +289,145 @@ def batched_workload(args):
             fh.write(line + "\n")
 
 
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1000.0 * (time.perf_counter() - t0) / reps
+
+
+def side_measurements(reps):
+    """Bounded measurements of the other workloads (each a few repetitions,
+    inputs resident in device memory before timing):
+    - 100k Gaussians, 800x800: forward Mrays/s with tiles in Morton order
+      against scanline ray order (Sec. 3.3 ray coherence);
+    - 3M Gaussians, outdoor layout, 4 views 1297x840: forward and
+      forward+backward Mrays/s;
+    - 1M Gaussians, 4 views 1024x768: the training workload with Adam and
+      the isotropic scale loss (weight 2.5e-4, r0 10, Sec. 4.2), rebuild every
+      step, graph-captured: steps/s;
+    - 5M Gaussians, 16 views of mixed size: the graph-captured training step
+      over one persistent launch (autotuned knobs), against the plain forward
+      of the 16 views launched one by one."""
+    import torch
+    from paper_2509_07782_amd import autotune, inputs
+    from paper_2509_07782_amd.render import Adam, RenderOptions, Renderer, TrainStep
+    keys = ("means", "log_scales", "quats", "density", "sh")
+    out = {}
+    adaptive = dict(adaptive=True, dt_min=0.005, dt_max=0.02, beta=1024.0, n_s=8, t_eps=1e-4, ess=1)
+
+    # ray order on the 100k scene
+    t0 = time.time()
+    sc = inputs.config_scene(2)
+    cams = inputs.config_cameras(2)
+    r = Renderer(0)
+    r.build({k: torch.from_numpy(sc[k]).cuda() for k in keys}, sc["sh_degree"])
+    R = sum(c.width * c.height for c in cams)
+    res = {}
+    for name, order in (("morton_tiles", 1), ("scanline", 0)):
+        o = RenderOptions(**adaptive, ray_order=order, persistent=True)
+        res[name] = R / (_timed(lambda: r.forward(cams, o), reps) * 1e-3) / 1e6
+    out["config2_fwd_mrays_s"] = res
+    r.check_errors()
+    r.close()
+    log(f"side: ray order done ({time.time() - t0:.1f}s)")
+
+    # outdoor layout, forward and forward + backward
+    t0 = time.time()
+    sc = inputs.config_scene(4)
+    cams = inputs.config_cameras(4)
+    r = Renderer(0)
+    params = {k: torch.from_numpy(sc[k]).cuda() for k in keys}
+    r.build(params, sc["sh_degree"])
+    R = sum(c.width * c.height for c in cams)
+    o = RenderOptions(**adaptive, persistent=True)
+    st = r.new_state()
+    gC = torch.full((R, 3), 1e-3, device="cuda")
+    ms_f = _timed(lambda: r.forward(cams, o), reps)
+
+    def fwd_bwd():
+        rgb, T = r.forward(cams, o, state=st)
+        r.backward(st, rgb, T, gC, None, params)
+    ms_fb = _timed(fwd_bwd, reps)
+    _, _, stats = r.forward(cams, o, stats=True, state=st)
+    tot = st.totals()
+    out["config4"] = {"fwd_mrays_s": R / (ms_f * 1e-3) / 1e6,
+                      "fwd_bwd_mrays_s": R / (ms_fb * 1e-3) / 1e6,
+                      "ms_fwd": ms_f, "ms_fwd_bwd": ms_fb,
+                      "per_ray": {k: tot[k] / tot["rays"] for k in ("Q", "P", "samples", "segments",
+                                                                   "closest", "box_only")},
+                      "chunked_segments": tot["chunked"]}
+    r.check_errors()
+    st.close()
+    r.close()
+    del params, gC
+    torch.cuda.empty_cache()
+    log(f"side: outdoor done ({time.time() - t0:.1f}s)")
+
+    # training workload with Adam, per-step rebuild, isotropic loss
+    t0 = time.time()
+    sc = inputs.config_scene(3)
+    cams = inputs.config_cameras(3)
+    R = sum(c.width * c.height for c in cams)
+    target = torch.from_numpy(inputs.target_image(3, R)).cuda()
+    r = Renderer(0)
+    p = {k: torch.from_numpy(sc[k]).cuda().requires_grad_(True) for k in keys}
+    step = TrainStep(r, p, sc["sh_degree"], cams, RenderOptions(**adaptive, persistent=True),
+                     lambda c, t: ((c - target) ** 2).mean(), optimizer=Adam(r, p),
+                     iso_weight=2.5e-4, iso_r0=10.0)
+    ms_t = _timed(step.replay, max(reps, 3))
+    out["train_adam"] = {"steps_per_s": 1000.0 / ms_t, "ms_per_step": ms_t,
+                         "mrays_s": R / (ms_t * 1e-3) / 1e6,
+                         "workload": "1M Gaussians, 4 views 1024x768, rebuild + forward + L2 + "
+                                     "2.5e-4 isotropic loss + backward + Adam, graph-captured"}
+    r.check_errors()
+    del step, p, target
+    r.close()
+    torch.cuda.empty_cache()
+    log(f"side: training done ({time.time() - t0:.1f}s)")
+
+    # batched persistent graph step against plain launches, 5M / 16 views
+    t0 = time.time()
+    sc = inputs.config_scene(5)
+    cams = inputs.config_cameras(5)
+    R = sum(c.width * c.height for c in cams)
+    target = torch.from_numpy(inputs.target_image(5, R)).cuda()
+    r = Renderer(0)
+    p = {k: torch.from_numpy(sc[k]).cuda().requires_grad_(True) for k in keys}
+    r.build({k: v.detach() for k, v in p.items()}, sc["sh_degree"])
+    base = RenderOptions(**adaptive, persistent=True)
+    # knobs tuned for the persistent launch on a quarter of the views (the
+    # candidates' images are checked bit for bit against the reference)
+    import tempfile
+    tuned, table = autotune.tune(r, cams[:4], base, reps=1, persistent=True,
+                                 cache_path=os.path.join(tempfile.gettempdir(), "rgx_autotune.json"))
+    plain = RenderOptions(**adaptive, persistent=False)
+    ms_plain = _timed(lambda: [r.forward([c], plain) for c in cams], reps)
+    ms_base_fwd = _timed(lambda: r.forward(cams, base), reps)
+    ms_tuned_fwd = _timed(lambda: r.forward(cams, tuned), reps)
+    step = TrainStep(r, p, sc["sh_degree"], cams, tuned, lambda c, t: ((c - target) ** 2).mean(),
+                     lr=0.0)
+    ms_graph = _timed(step.replay, reps)
+    r.check_errors()
+    out["workload5"] = {"rays": R,
+                        "graph_fwd_bwd_step_mrays_s": R / (ms_graph * 1e-3) / 1e6,
+                        "batched_fwd_mrays_s": R / (ms_tuned_fwd * 1e-3) / 1e6,
+                        "batched_fwd_fixed_knobs_mrays_s": R / (ms_base_fwd * 1e-3) / 1e6,
+                        "plain_fwd_16_launches_mrays_s": R / (ms_plain * 1e-3) / 1e6,
+                        "autotuned_knobs": {k: getattr(tuned, k) for k in
+                                            ("tile_w", "tile_h", "persistent", "window_segments")}}
+    r.check_errors()
+    del step, p, target
+    r.close()
+    torch.cuda.empty_cache()
+    log(f"side: workload 5 done ({time.time() - t0:.1f}s)")
+    return out
+
+
 def cpu_baseline(scene, cams, opts, stride):
     """The FP64 oracle (forward and adjoint of the L2 loss) on every
     stride-th pixel of every view, in the same rays-per-second unit."""
@@ -297,7 +445,17 @@ def cpu_baseline(scene, cams, opts, stride):
         oracle.backward(scene, cam, o, pix, gC, None)
         nr += len(pix)
     dt = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": nr / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
+            "host_cpu": model, "host_cpus_online": os.cpu_count(),
             "kind": "oracle", "seconds": dt,
             "sample": f"every {stride}th pixel on both axes of the 4 views ({nr} rays), "
                       "forward + adjoint"}

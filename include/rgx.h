@@ -65,6 +65,14 @@ typedef struct rgx_context rgx_context;
    ellipsoids' minimal AABBs (Supp. B).  Rebuilding reuses its memory. */
 typedef struct rgx_bvh rgx_bvh;
 
+/* Forward state kept for the backward (Alg. 1 run forwards, then its adjoint):
+   which structure build, cameras and options the forward rendered, and what
+   its searches found -- each ray's first closest-hit results (Eq. 4) and every
+   window list its tiles collected -- so that the backward replays them instead
+   of searching again.  Owned by the caller (rgx_fwd_destroy); it holds no
+   pointer to a caller buffer. */
+typedef struct rgx_fwd rgx_fwd;
+
 typedef struct {
   int64_t n;                 /* number of Gaussians, >= 1 */
   int32_t sh_degree;         /* 0..3 */
@@ -73,6 +81,15 @@ typedef struct {
   const float *quats;        /* [n,4] (w,x,y,z) */
   const float *density;      /* [n]   sigma~ */
   const float *sh;           /* [n,K,3] */
+  /* Optional spherical-Gaussian colour lobes (the 9 SH + 7 SG appearance
+     model of the supplement's comparison with 3D-GS): the colour at unit
+     direction d becomes c(d) = sum_m f_m Y_m(d) + sum_j a_j
+     exp(lambda_j (xi_j.d / |xi_j| - 1)).  n_sg = 0 (sg ignored) or 1..7;
+     sg [n, n_sg, 7] per lobe (a_r, a_g, a_b, xi_x, xi_y, xi_z, lambda), the
+     axis of any non-zero norm (a zero axis makes the lobe absent).  Lobes
+     need rgx_render_opts.n_s = 8. */
+  int32_t n_sg;
+  const float *sg;
 } rgx_gaussians;
 
 typedef struct {
@@ -102,10 +119,15 @@ typedef struct {
   int32_t window_segments;   /* initial depth-window length, in longest segments (0: 1);
                                 tuning only, never changes results */
   float bg[3];               /* background colour added with the final transmittance */
+  int32_t no_record;         /* 1: a forward given a state keeps only its cameras and options,
+                                not its searches (the backward then searches again, with the
+                                same results); never changes results */
 } rgx_render_opts;
 
 typedef struct {             /* gradient outputs, user order, float32 */
+  int64_t n;                 /* rows of every buffer below; must equal the structure's n */
   float *means, *log_scales, *quats, *density, *sh;  /* [n,3] [n,3] [n,4] [n] [n,K,3] */
+  float *sg;                 /* [n, n_sg, 7] lobe gradients, required when the structure has lobes */
   int32_t accumulate;        /* 0: overwrite, 1: add into the buffers */
   /* Densification statistic of Sec. 3.5 (Eq. 12), nullable: for each view v
      of the call, densify[i] += alpha_v |dL_v/dmu_i| with alpha_v =
@@ -132,12 +154,32 @@ enum {
   RGX_STAT_LEAVES,       /* leaves the wave visited for the segment collections */
   RGX_STAT_WINDOWS,      /* window collections the wave made (attempts included) */
   RGX_STAT_CHUNKED,      /* segments whose candidates were collected in several Z chunks */
-  RGX_STAT_CAND,         /* per wave: candidates passing the window list's depth pre-check */
+  RGX_STAT_CAND,         /* per wave: candidates passing the window list's depth pre-checks
+                            (the wave's span, then some lane's own segment) */
   RGX_STAT_CAND_HIT,     /* per wave: candidates that some lane hit */
   RGX_STAT_KCYC_COLLECT, /* per wave: shader-clock kilocycles in window collection */
   RGX_STAT_KCYC_CLOSEST, /* per wave: kilocycles in closest-hit queries */
   RGX_STAT_KCYC_TILE,    /* per wave: kilocycles for the whole tile */
-  RGX_NSTAT = 15
+  RGX_STAT_T_END,        /* float bits: where the ray's march ended (Alg. 1): the start of the
+                            first segment with T <= T_eps, else t_far */
+  RGX_NSTAT = 16
+};
+
+/* Totals of one forward's per-ray statistics, returned by rgx_sync_stats */
+enum {
+  RGX_TOT_RAYS = 0,      /* rays rendered */
+  RGX_TOT_Q,             /* sum of RGX_STAT_Q */
+  RGX_TOT_P,             /* sum of RGX_STAT_P */
+  RGX_TOT_SAMPLES,       /* sum of RGX_STAT_SAMPLES */
+  RGX_TOT_SEGMENTS,      /* sum of RGX_STAT_SEGMENTS */
+  RGX_TOT_CLOSEST,       /* sum of RGX_STAT_CLOSEST */
+  RGX_TOT_NODES,         /* BVH nodes loaded for window collections, summed over waves */
+  RGX_TOT_BOX_ONLY,      /* sum of RGX_STAT_BOX_ONLY (AABB-only leaves per window collection) */
+  RGX_TOT_CHUNKED,       /* segments whose window list overflowed and was taken in Z chunks */
+  RGX_TOT_INACTIVE,      /* Gaussians of the structure that are inactive */
+  RGX_TOT_UNRECORDED,    /* 64-ray tiles whose searches did not fit the state's record (their
+                            backward searches again, with the same results) */
+  RGX_NTOT = 11
 };
 
 /* Create / destroy a context on HIP device `device`.  rgx_create allocates. */
@@ -167,32 +209,60 @@ int64_t rgx_bvh_size(const rgx_bvh *bvh);
 
 /* Forward render of n_views views (host array) through Algorithm 1.
    out_rgb [R,3] and out_T [R] with R = sum of width*height; `stats`
-   (nullable) receives [R, RGX_NSTAT] int32 counters.  With empty-space
-   skipping on (and the BVH in use), the forward also records, keyed by the
-   structure, its build, the cameras and the options, in context-owned
-   buffers grown on demand (outgrown ones are kept until rgx_destroy):
-   each ray's first four closest-hit results (Alg. 1 ClosestHit, Eq. 4;
-   16 B per ray) and every window list its tiles collected (a shared pool of
-   48 KB per 64-ray tile; a tile that does not fit is not recorded). */
+   (nullable) receives [R, RGX_NSTAT] int32 counters.
+
+   state: NULL renders only (nothing is recorded; no backward can follow).
+   Otherwise *state receives the forward state needed by rgx_render_backward:
+   a new handle when *state is NULL, else the given handle is reused in place
+   (its buffers grow when needed and are kept, so a forward with a reused
+   handle can be captured into a graph once a first call has sized them).
+   With empty-space skipping on (and the BVH in use) the state records each
+   ray's first four closest-hit results (Alg. 1 ClosestHit, Eq. 4; 16 B per
+   ray) and every window list its tiles collected (a pool of 48 KB per 64-ray
+   tile on average; a tile that does not fit is not recorded and its backward
+   searches again, with the same results).  With `stats` given, the state
+   also receives the totals that rgx_sync_stats returns.  Any number of states
+   may be outstanding; each belongs to one forward at a time. */
 rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
                               int32_t n_views, const rgx_render_opts *opts, float *out_rgb,
-                              float *out_T, int32_t *stats, hipStream_t stream);
+                              float *out_T, int32_t *stats, rgx_fwd **state, hipStream_t stream);
 
-/* Backward of rgx_render_forward: given the forward outputs (out_rgb, out_T
-   exactly as returned) and dL/d(out_rgb) [R,3], dL/d(out_T) [R] (nullable),
-   writes dL/d(parameters) in user order.  The sample schedule, the ESS
-   restarts and the truncation boundaries are treated as constants.  The
-   segments are re-traversed in the forward's deterministic order; the
+/* Backward of the forward that filled `state` (adjoint of Eq. 3 along
+   Algorithm 1): given that forward's outputs (out_rgb, out_T exactly as
+   returned) and dL/d(out_rgb) [R,3], dL/d(out_T) [R] (nullable), writes
+   dL/d(parameters) in user order.  The cameras and options are the state's.
+   The sample schedule, the ESS restarts and the truncation boundaries are
+   treated as constants.  Segments are taken in the forward's deterministic
+   order, the recorded closest hits and window lists replayed; the
    transmittance before every sample is recomputed, and the colour still to
-   come behind a sample is the final colour minus the running prefix.  When
-   the context's last forward rendered the same structure build, cameras and
-   options, its recorded closest-hit results and window lists are replayed
-   instead of searched again (same values, so the same segments); calls that
-   overlap on one context race on that record. */
-rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
-                               int32_t n_views, const rgx_render_opts *opts, const float *out_rgb,
-                               const float *out_T, const float *grad_rgb, const float *grad_T,
-                               const rgx_grads *grads, hipStream_t stream);
+   come behind a sample is the final colour minus the running prefix.
+   RGX_ERR_STATE when `bvh` is not the structure build the forward rendered
+   (rebuilt or replaced since) or the state belongs to another context;
+   RGX_ERR_INVALID_ARG when grads->n differs from the structure's n. */
+rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_fwd *state,
+                               const float *out_rgb, const float *out_T, const float *grad_rgb,
+                               const float *grad_T, const rgx_grads *grads, hipStream_t stream);
+
+/* Releases a forward state and its device memory (NULL is a no-op).  The
+   caller makes sure no enqueued or captured work still uses it. */
+void rgx_fwd_destroy(rgx_fwd *state);
+
+/* (host) Waits for `stream` (the one the state's forward ran on) and writes
+   the totals of that forward's statistics, out[RGX_NTOT].  RGX_ERR_STATE when
+   the forward was not given a `stats` buffer. */
+rgx_status rgx_sync_stats(rgx_context *ctx, const rgx_fwd *state, int64_t *out,
+                          hipStream_t stream);
+
+/* AABB false positives along whole rays (Sec. 3.4, Eq. 6; minimal AABB of
+   Supp. B): for the rays `pix` (row-major pixel indices of the single view
+   `cam`), count[i] = the number of active Gaussians whose minimal AABB
+   mu +/- L, L_j = k sqrt(sum_m r_jm^2 s_m^2), meets the ray over
+   [t_near, t_end[i]] (slab test) while the ellipsoid's chord does not.
+   t_end [n_rays] device float, e.g. RGX_STAT_T_END of a forward.  Counts
+   int32 [n_rays] device.  A statistics path, not used by the renderer. */
+rgx_status rgx_false_positives(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cam,
+                               const int32_t *pix, int32_t n_rays, const float *t_end,
+                               int32_t *count, hipStream_t stream);
 
 /* Debug: per-ray hit sets.  For the rays `pix` (row-major pixel indices of
    the single view `cam`), records every (segment start, Gaussian) pair of
@@ -223,9 +293,14 @@ rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *bvh, uint64_t *keys, i
                          hipStream_t stream);
 
 /* Debug: device-side error flag of the context (synchronises the stream).
-   flags[0] != 0 means results are invalid: 1 a closest-hit stack overflowed,
-   2 a traversal visited more nodes than the tree has, 3 a malformed node,
-   4 a segment made no progress in FP32, 5 a broken window-list record. */
+   flags[0] != 0 means results are invalid.  Every flag guards a condition
+   that a structure built by rgx_build_bvh and arguments the host checks
+   accept cannot reach (the stacks are sized for the deepest possible tree,
+   segment lengths are checked against the FP32 resolution at t_far, and
+   list and record overflows are handled by chunking and re-searching): 1 a
+   closest-hit stack overflowed, 2 a traversal visited more nodes than the
+   tree has, 3 a malformed node, 4 a segment made no progress in FP32, 5 a
+   broken window-list record, 6 a false-positive walk's stack overflowed. */
 rgx_status rgx_error_flags(rgx_context *ctx, int32_t *flags /*host*/, hipStream_t stream);
 
 /* Isotropic scale loss (Sec. 3.4, Eq. 8, with the volume-ratio bound of
@@ -253,6 +328,25 @@ rgx_status rgx_isotropic_loss_noalloc(rgx_context *ctx, int64_t n, const float *
                                       float r0, float *loss, float *grad, int32_t accumulate,
                                       hipStream_t stream);
 
+/* One parameter array of an Adam step (host struct). */
+typedef struct {
+  int64_t n;                 /* floats in the arrays, >= 0 */
+  float *param;              /* [n] updated in place */
+  const float *grad;         /* [n] */
+  float *m, *v;              /* [n] first and second moments, zero before the first step */
+  float lr;                  /* learning rate of this array */
+} rgx_adam_group;
+
+/* Adam (Kingma and Ba, 2015), the optimizer of the training workload (the
+   per-step rebuild of Sec. 5 / Supp. F is rgx_build_bvh): advances the
+   device step counter *step (int32, zero before the first step) by one, then
+   for every element of every group m = b1 m + (1 - b1) g, v = b2 v + (1 - b2)
+   g^2, p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t the new
+   count.  The counter lives on the device, so a captured step replays with
+   the right bias corrections.  groups is a host array of n_groups >= 1. */
+rgx_status rgx_adam_step(rgx_context *ctx, const rgx_adam_group *groups, int32_t n_groups,
+                         int32_t *step, float beta1, float beta2, float eps, hipStream_t stream);
+
 /* Optional kernel timing, for measurement.  While enabled, every launch made
    by rgx_build_bvh, rgx_render_forward and rgx_render_backward is bracketed
    by two HIP events recorded on the caller's stream (so the interval is that
@@ -271,8 +365,8 @@ rgx_status rgx_set_kernel_timing(rgx_context *ctx, int32_t enable);
    (host arrays).  reset != 0 clears the record afterwards. */
 rgx_status rgx_kernel_times(rgx_context *ctx, double *ms, int64_t *launches, int32_t reset);
 
-/* (host) 1 if the context's last rgx_render_backward replayed the closest-hit
-   results of its forward, 0 if it searched them itself. */
+/* (host) 1 if the context's last rgx_render_backward replayed its forward's
+   recorded searches, 0 if the state held no record and it searched itself. */
 int32_t rgx_backward_replayed(const rgx_context *ctx);
 
 const char *rgx_status_string(rgx_status s);

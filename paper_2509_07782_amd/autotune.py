@@ -42,19 +42,22 @@ def _time(fn, reps):
 
 
 def tune(renderer: Renderer, cams, opts: RenderOptions, reps: int = 2,
-         cache_path: str | None = None, with_backward: bool = False, params=None):
-    """Returns the fastest equivalent RenderOptions (and the timing table)."""
-    key = cache_key(renderer, cams, opts)
+         cache_path: str | None = None, with_backward: bool = False, params=None,
+         persistent: bool | None = None):
+    """Returns the fastest equivalent RenderOptions (and the timing table).
+    persistent: None searches both launch forms, True / False fixes it."""
+    key = cache_key(renderer, cams, opts) + f"|pers{persistent}"
     if cache_path and os.path.exists(cache_path) and key not in _CACHE:
         with open(cache_path) as fh:
             _CACHE.update(json.load(fh))
     if key in _CACHE:
         return dataclasses.replace(opts, **_CACHE[key]["knobs"]), _CACHE[key]["table"]
     ref_rgb, ref_T = renderer.forward(cams, opts)
+    st = renderer.new_state() if with_backward else None
     table = []
     best = None
     for (tw, th) in TILES:
-        for pers in (False, True):
+        for pers in ((False, True) if persistent is None else (bool(persistent),)):
             for win in WINDOWS:
                 cand = dataclasses.replace(opts, ray_order=1, tile_w=tw, tile_h=th,
                                            persistent=pers, window_segments=win)
@@ -63,10 +66,10 @@ def tune(renderer: Renderer, cams, opts: RenderOptions, reps: int = 2,
                     raise RuntimeError(f"tuning knobs changed the image: {cand}")
 
                 def run():
-                    out = renderer.forward(cams, cand)
+                    out = renderer.forward(cams, cand, state=st if with_backward else None)
                     if with_backward:
                         g = torch.full_like(out[0], 1e-3)
-                        renderer.backward(cams, cand, out[0], out[1], g, None, params)
+                        renderer.backward(st, out[0], out[1], g, None, params)
                     return out
 
                 t = _time(run, reps)
@@ -74,6 +77,8 @@ def tune(renderer: Renderer, cams, opts: RenderOptions, reps: int = 2,
                 table.append((knobs, t))
                 if best is None or t < best[1]:
                     best = (knobs, t)
+    if st is not None:
+        st.close()
     _CACHE[key] = {"knobs": best[0], "table": [(k, t) for k, t in table]}
     if cache_path:
         with open(cache_path, "w") as fh:

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "build.hip", "march.hip", "loss.hip"]
+SOURCES = ["march.hip", "api.hip", "build.hip", "loss.hip", "optim.hip"]
 LIB = os.path.join(HERE, "librgx.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -21,6 +21,7 @@ static_assert(RGX_STAT_Q == ST_Q && RGX_STAT_P == ST_P && RGX_STAT_SAMPLES == ST
                   RGX_STAT_BOX_ONLY == ST_BOX_ONLY && RGX_STAT_NODES == ST_NODES &&
                   RGX_STAT_LEAVES == ST_LEAVES && RGX_STAT_WINDOWS == ST_WINDOWS &&
                   RGX_STAT_CHUNKED == ST_CHUNKED && RGX_STAT_KCYC_TILE == ST_KCYC_TILE &&
+                  RGX_STAT_T_END == ST_T_END &&
                   RGX_NSTAT == kNStat,
               "stat slots");
 static_assert(RGX_MAX_GAUSSIANS == RGX_MAX_GAUSSIANS_INTERNAL, "size limit");
@@ -47,11 +48,7 @@ struct rgx_context {
   size_t ev_used = 0;
   double *partial = nullptr;        // per-block partial sums of rgx_isotropic_loss
   int64_t partial_cap = 0;
-  DevBuf replay;                    // closest-hit results recorded by the last forward
-  DevBuf wrec;                      // its window lists (shared pool, counter first)
-  DevBuf wrec_tile;                 // per tile: (complete, first chunk)
-  uint64_t replay_key = 0;          // what that forward rendered (0: nothing recorded)
-  std::vector<void *> retired;      // outgrown replay buffers: a captured graph may still use them
+  uint64_t build_serial = 0;        // bumped by every build on the context: names a structure build
   int32_t replayed = 0;             // whether the last backward replayed
   double *iso_scratch = nullptr;    // device address of the fixed loss workspace on this device
 };
@@ -84,12 +81,32 @@ struct rgx_bvh {
   rgx_context *ctx = nullptr;
   int64_t n = 0, cap = 0;
   int32_t sh_degree = 0, sh_k = 1, col_stride = 4, col_cap = 0;
+  int32_t n_sg = 0;                 // spherical-Gaussian lobes per Gaussian
   float sigma_eps = 0.01f;
   int morton_bits = 21;
   int sorted_sel = 0;
-  uint64_t generation = 0;          // bumped by every build: keys the closest-hit replay
+  uint64_t serial = 0;              // the context's build serial of the current contents
   DevBuf geom_user, aabb_user, aux_user, aux, active, bounds, counters, keys0, keys1, vals0, vals1, hist, geom,
-      aabb, col, nodes, nodes4, seg, parent, acc, zprev;
+      aabb, col, nodes, nodes4, seg, parent, acc, zsum, sg_user, sgrec, sgacc;
+};
+
+// Forward state: what one forward rendered and what its searches found.
+struct rgx_fwd {
+  rgx_context *ctx = nullptr;       // compared only: the state may outlive its context
+  int device = 0;                   // the context's device, for rgx_fwd_destroy
+  const rgx_bvh *bvh = nullptr;     // compared, never dereferenced (the structure may be gone)
+  uint64_t serial = 0;              // build serial the forward rendered
+  int64_t n = 0;                    // Gaussians of that build
+  std::vector<rgx_camera> cams;
+  rgx_render_opts opts;
+  int64_t rays = 0, tiles = 0;
+  bool recorded = false;            // closest hits and window lists recorded
+  bool has_totals = false;          // statistics totals reduced into `totals`
+  DevBuf replay;                    // [rays][kReplayK] closest-hit results
+  DevBuf wrec;                      // window-list pool (64-bit counter first)
+  DevBuf wrec_tile;                 // per tile: (complete, first record)
+  DevBuf totals;                    // int64 [RGX_NTOT]
+  std::vector<void *> retired;      // outgrown buffers: a captured graph may still use them
 };
 
 static rgx_status fail(rgx_context *ctx, rgx_status s, const std::string &msg) {
@@ -106,6 +123,14 @@ static rgx_status hip_fail(rgx_context *ctx, hipError_t e, const char *where) {
     hipError_t e_ = (expr);                                 \
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);  \
   } while (0)
+
+// Makes `device` current and clears an error left pending by earlier HIP
+// calls outside the library, so that the launch checks of this call report
+// only this call's own errors.
+static hipError_t enter(int device) {
+  (void)hipGetLastError();
+  return hipSetDevice(device);
+}
 
 static hipError_t ensure(DevBuf &b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return hipSuccess;
@@ -173,10 +198,6 @@ void rgx_destroy(rgx_context *ctx) {
   if (ctx->queue) (void)hipFree(ctx->queue);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->partial) (void)hipFree(ctx->partial);
-  if (ctx->replay.p) (void)hipFree(ctx->replay.p);
-  if (ctx->wrec.p) (void)hipFree(ctx->wrec.p);
-  if (ctx->wrec_tile.p) (void)hipFree(ctx->wrec_tile.p);
-  for (void *p : ctx->retired) (void)hipFree(p);
   delete ctx;
 }
 
@@ -184,7 +205,8 @@ void rgx_bvh_destroy(rgx_bvh *b) {
   if (!b) return;
   DevBuf *all[] = {&b->geom_user, &b->aabb_user, &b->aux_user, &b->aux, &b->active, &b->bounds, &b->counters, &b->keys0,
                    &b->keys1, &b->vals0, &b->vals1, &b->hist, &b->geom, &b->aabb, &b->col,
-                   &b->nodes, &b->nodes4, &b->seg, &b->parent, &b->acc, &b->zprev};
+                   &b->nodes, &b->nodes4, &b->seg, &b->parent, &b->acc, &b->zsum,
+                   &b->sg_user, &b->sgrec, &b->sgacc};
   for (DevBuf *d : all) release(*d);
   delete b;
 }
@@ -201,12 +223,14 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
     return fail(ctx, RGX_ERR_INVALID_ARG, "sh_degree must be 0..3");
   if (!g->means || !g->log_scales || !g->quats || !g->density || !g->sh)
     return fail(ctx, RGX_ERR_INVALID_ARG, "null parameter array");
+  if (g->n_sg < 0 || g->n_sg > kMaxSg || (g->n_sg > 0 && !g->sg))
+    return fail(ctx, RGX_ERR_INVALID_ARG, "n_sg must be 0..7, with sg given when > 0");
   const float sigma_eps = opts ? opts->sigma_eps : 0.01f;
   const int bits = (opts && opts->morton_bits) ? opts->morton_bits : 21;
   if (!(sigma_eps > 0.0f) || !std::isfinite(sigma_eps))
     return fail(ctx, RGX_ERR_INVALID_ARG, "sigma_eps must be > 0");
   if (bits < 1 || bits > 21) return fail(ctx, RGX_ERR_INVALID_ARG, "morton_bits must be 1..21");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   rgx_bvh *b = *bvh;
   const bool fresh = b == nullptr;
   if (fresh) {
@@ -243,6 +267,11 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   ENS(seg, (size_t)(2 * P) * 6 * 4);
   ENS(parent, (size_t)(2 * n) * 4);
   ENS(acc, (size_t)n * kAccFloats * 4);
+  if (g->n_sg > 0) {
+    ENS(sg_user, (size_t)n * kSgFloats * 4);
+    ENS(sgrec, (size_t)n * kSgFloats * 4);
+    ENS(sgacc, (size_t)n * kSgAccFloats * 4);
+  }
 #undef ENS
   if (e != hipSuccess) {
     if (fresh) rgx_bvh_destroy(b);
@@ -250,16 +279,21 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
                 std::string("allocation: ") + hipGetErrorString(e));
   }
   b->n = n;
-  b->generation++;
+  b->serial = ++ctx->build_serial;
   b->sh_degree = g->sh_degree;
   b->sh_k = sh_k;
   b->col_stride = col_stride;
   b->sigma_eps = sigma_eps;
   b->morton_bits = bits;
+  b->n_sg = g->n_sg;
   BuildArgs a;
   a.n = n;
   a.means = g->means; a.log_scales = g->log_scales; a.quats = g->quats; a.density = g->density;
   a.sh = g->sh;
+  a.sg = g->sg;
+  a.n_sg = g->n_sg;
+  a.sg_user = (float *)b->sg_user.p;
+  a.sgrec = (float *)b->sgrec.p;
   a.sh_k = sh_k; a.col_stride = col_stride; a.morton_bits = bits; a.sigma_eps = sigma_eps;
   a.geom_user = (float *)b->geom_user.p; a.aabb_user = (float *)b->aabb_user.p;
   a.aux_user = (float *)b->aux_user.p; a.aux = (float *)b->aux.p;
@@ -275,7 +309,9 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   a.parent = (int32_t *)b->parent.p;
   e = timed(ctx, RGX_KERN_BUILD, stream, [&] {
     hipError_t r = launch_build(a, stream);
-    return r == hipSuccess ? launch_fill(b->acc.p, n * kAccFloats, 0u, stream) : r;
+    if (r == hipSuccess) r = launch_fill(b->acc.p, n * kAccFloats, 0u, stream);
+    if (r == hipSuccess && g->n_sg > 0) r = launch_fill(b->sgacc.p, n * kSgAccFloats, 0u, stream);
+    return r;
   });
   if (e != hipSuccess) {
     if (fresh) rgx_bvh_destroy(b);
@@ -300,6 +336,8 @@ static SceneDev scene_of(const rgx_bvh *b) {
   s.counters = (const int32_t *)b->counters.p;
   s.perm = (const uint32_t *)(b->sorted_sel ? b->vals1.p : b->vals0.p);
   s.aux = (const float *)b->aux.p;
+  s.sg = b->n_sg > 0 ? (const float *)b->sgrec.p : nullptr;
+  s.n_sg = b->n_sg;
   s.n = b->n;
   return s;
 }
@@ -350,6 +388,8 @@ static rgx_status make_opts(rgx_context *ctx, const rgx_bvh *b, const rgx_render
   for (int i = 0; i < 3; i++) m.bg[i] = o->bg[i];
   m.sh_k = b->sh_k;
   m.col_stride = b->col_stride;
+  if (b->n_sg > 0 && m.n_s != 8)
+    return fail(ctx, RGX_ERR_UNSUPPORTED, "spherical-Gaussian colour lobes need n_s = 8");
   return RGX_OK;
 }
 
@@ -420,6 +460,14 @@ static rgx_status view_tables(rgx_context *ctx, const rgx_camera *cams, int n_vi
         s = tile_order(ctx, c.width, c.height, m.tile_w, m.tile_h, &V.tile_order);
         if (s != RGX_OK) return s;
       }
+      {
+        // every segment must advance in FP32 up to t_far: its length N_s dt
+        // (at least N_s dt_min in adaptive mode) above twice the spacing of
+        // floats near t_far, so that a + N_s dt > a for every a < t_far
+        const double seg_min = (double)m.n_s * (m.adaptive ? m.dt_min : m.dt);
+        if (seg_min < std::ldexp((double)c.t_far, -21))
+          return fail(ctx, RGX_ERR_INVALID_ARG, "segment length below the FP32 resolution at t_far");
+      }
       if (!m.adaptive) {
         // fixed-step sample positions come from exact integer-to-float products
         const double segs = ((double)c.t_far - (double)c.t_near) / ((double)m.dt * m.n_s);
@@ -446,38 +494,17 @@ static rgx_status view_tables(rgx_context *ctx, const rgx_camera *cams, int n_vi
   return RGX_OK;
 }
 
-// FNV-1a over what decides a march's closest-hit queries: the structure
-// (and its build generation), the cameras and the options.
-static uint64_t march_key(const rgx_bvh *b, const rgx_camera *cams, int32_t n_views,
-                          const MarchOpts &m) {
-  uint64_t h = 1469598103934665603ull;
-  auto mix = [&h](const void *p, size_t n) {
-    const unsigned char *c = (const unsigned char *)p;
-    for (size_t i = 0; i < n; i++) { h ^= c[i]; h *= 1099511628211ull; }
-  };
-  MarchOpts k;
-  memcpy(&k, &m, sizeof k);
-  k.replay_mode = 0;
-  k.replay = nullptr;
-  mix(&b, sizeof b);
-  mix(&b->generation, sizeof b->generation);
-  mix(&n_views, sizeof n_views);
-  mix(cams, sizeof(rgx_camera) * (size_t)n_views);
-  mix(&k, sizeof k);
-  return h ? h : 1;
-}
-
-// Grows a record buffer to at least `need` bytes; an outgrown buffer is kept
-// until rgx_destroy (a captured graph may hold its address).
-static bool grow_record(rgx_context *ctx, DevBuf &b, size_t need) {
+// Grows a state's record buffer to at least `need` bytes; an outgrown buffer
+// is kept until rgx_fwd_destroy (a captured graph may hold its address).
+static bool grow_record(rgx_fwd *f, DevBuf &b, size_t need) {
   if (b.bytes >= need) return true;
   void *p = nullptr;
   const size_t bytes = std::max(need, 2 * b.bytes);
   if (hipMalloc(&p, bytes) != hipSuccess) {
-    (void)hipGetLastError();   // an allocation failure only disables the replay
+    (void)hipGetLastError();   // an allocation failure only disables the record
     return false;
   }
-  if (b.p) ctx->retired.push_back(b.p);
+  if (b.p) f->retired.push_back(b.p);
   b.p = p;
   b.bytes = bytes;
   return true;
@@ -504,12 +531,15 @@ extern "C" {
 
 rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
                               int32_t n_views, const rgx_render_opts *opts, float *out_rgb,
-                              float *out_T, int32_t *stats, hipStream_t stream) {
+                              float *out_T, int32_t *stats, rgx_fwd **state, hipStream_t stream) {
   if (!ctx || !bvh || !out_rgb || !out_T) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  if (bvh->ctx != ctx) return fail(ctx, RGX_ERR_STATE, "structure built on another context");
+  if (state && *state && (*state)->ctx != ctx)
+    return fail(ctx, RGX_ERR_STATE, "forward state of another context");
   MarchOpts m;
   rgx_status s = make_opts(ctx, bvh, opts, m);
   if (s != RGX_OK) return s;
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   std::vector<ViewTable> tabs;
   if ((s = view_tables(ctx, cams, n_views, m, tabs)) != RGX_OK) return s;
   const SceneDev sd = scene_of(bvh);
@@ -518,61 +548,96 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
   out.rgb = out_rgb;
   out.T = out_T;
   out.stats = stats;
-  // record the closest-hit results for a backward over the same rays; the
-  // buffer only grows, and an outgrown one stays allocated until rgx_destroy
-  // (a captured graph may hold its address)
-  const uint64_t key = march_key(bvh, cams, n_views, m);
-  ctx->replay_key = 0;
   int64_t tiles = 0;
   for (const ViewTable &t : tabs) tiles += t.n_tiles;
-  const size_t need = (size_t)total_rays(cams, n_views) * kReplayK * sizeof(float);
-  const size_t pool = std::min<size_t>(2 + (size_t)tiles * kWrecDwordsPerTile, 0xfffffff0u);
-  if (m.ess && !m.brute_force && grow_record(ctx, ctx->replay, need) &&
-      grow_record(ctx, ctx->wrec, pool * sizeof(uint32_t)) &&
-      grow_record(ctx, ctx->wrec_tile, (size_t)tiles * 2 * sizeof(uint32_t))) {
-    m.replay_mode = 1;
-    m.replay = (float *)ctx->replay.p;
-    m.wrec = (uint32_t *)ctx->wrec.p;
-    m.wrec_tile = (uint32_t *)ctx->wrec_tile.p;
-    m.wrec_cap = (uint32_t)pool;
-    // the pool's 64-bit allocation counter (dwords 0-1) starts past itself
-    // (fill kernels, not memset nodes, so the call can be captured)
-    HIP_TRY(ctx, launch_fill(ctx->wrec.p, 1, 2u, stream));
-    HIP_TRY(ctx, launch_fill((uint32_t *)ctx->wrec.p + 1, 1, 0u, stream));
+  const int64_t rays = total_rays(cams, n_views);
+  rgx_fwd *f = nullptr;
+  if (state) {
+    f = *state ? *state : new rgx_fwd();
+    f->ctx = ctx;
+    f->device = ctx->device;
+    f->bvh = bvh;
+    f->serial = bvh->serial;
+    f->n = bvh->n;
+    f->cams.assign(cams, cams + n_views);
+    f->opts = *opts;
+    f->rays = rays;
+    f->tiles = tiles;
+    f->recorded = false;
+    f->has_totals = false;
+    // record the searches for the backward: each ray's first closest-hit
+    // results and every window list of every tile
+    const size_t need = (size_t)rays * kReplayK * sizeof(float);
+    // a shared pool: 48 KB per tile on average, at least 64 MB so that a
+    // call of few tiles with long window lists still records them all
+    const size_t pool = std::min<size_t>(
+        std::max<size_t>(2 + (size_t)tiles * kWrecDwordsPerTile, (size_t)1 << 24), 0xfffffff0u);
+    if (m.ess && !m.brute_force && !opts->no_record && grow_record(f, f->replay, need) &&
+        grow_record(f, f->wrec, pool * sizeof(uint32_t)) &&
+        grow_record(f, f->wrec_tile, (size_t)tiles * 2 * sizeof(uint32_t))) {
+      m.replay_mode = 1;
+      m.replay = (float *)f->replay.p;
+      m.wrec = (uint32_t *)f->wrec.p;
+      m.wrec_tile = (uint32_t *)f->wrec_tile.p;
+      m.wrec_cap = (uint32_t)pool;
+      // the pool's 64-bit allocation counter (dwords 0-1) starts past itself
+      // (fill kernels, not memset nodes, so the call can be captured)
+      hipError_t e = launch_fill(f->wrec.p, 1, 2u, stream);
+      if (e == hipSuccess) e = launch_fill((uint32_t *)f->wrec.p + 1, 1, 0u, stream);
+      if (e != hipSuccess) {
+        if (!*state) rgx_fwd_destroy(f);
+        return hip_fail(ctx, e, "record reset");
+      }
+      f->recorded = true;
+    }
+    if (stats && !grow_record(f, f->totals, RGX_NTOT * sizeof(int64_t))) {
+      if (!*state) rgx_fwd_destroy(f);
+      return fail(ctx, RGX_ERR_OUT_OF_MEMORY, "statistics totals");
+    }
+    *state = f;
   }
   for (const ViewTable &t : tabs) {
     if (t.n_tiles == 0) continue;
     HIP_TRY(ctx, timed(ctx, RGX_KERN_FORWARD, stream,
                        [&] { return launch_forward(sd, t, m, out, shape_for(ctx, m, t.n_tiles, fwd_waves_per_cu(m)), stream); }));
   }
-  if (m.replay_mode == 1) ctx->replay_key = key;
+  if (f && stats) {
+    HIP_TRY(ctx, launch_stat_totals(stats, rays, sd, f->recorded ? (const uint32_t *)f->wrec_tile.p : nullptr,
+                                    tiles, (int64_t *)f->totals.p, stream));
+    f->has_totals = true;
+  }
   return RGX_OK;
 }
 
-rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
-                               int32_t n_views, const rgx_render_opts *opts, const float *out_rgb,
-                               const float *out_T, const float *grad_rgb, const float *grad_T,
-                               const rgx_grads *grads, hipStream_t stream) {
-  if (!ctx || !bvh || !out_rgb || !out_T || !grad_rgb || !grads)
+rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_fwd *f,
+                               const float *out_rgb, const float *out_T, const float *grad_rgb,
+                               const float *grad_T, const rgx_grads *grads, hipStream_t stream) {
+  if (!ctx || !bvh || !f || !out_rgb || !out_T || !grad_rgb || !grads)
     return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
   if (!grads->means || !grads->log_scales || !grads->quats || !grads->density || !grads->sh)
     return fail(ctx, RGX_ERR_INVALID_ARG, "null gradient buffer");
+  if (f->ctx != ctx || bvh->ctx != ctx) return fail(ctx, RGX_ERR_STATE, "state of another context");
+  if (f->bvh != bvh || f->serial != bvh->serial)
+    return fail(ctx, RGX_ERR_STATE, "the structure was rebuilt or replaced since the forward");
+  if (grads->n != bvh->n) return fail(ctx, RGX_ERR_INVALID_ARG, "gradient buffers do not match the structure's n");
+  if (bvh->n_sg > 0 && !grads->sg) return fail(ctx, RGX_ERR_INVALID_ARG, "the structure has lobes: grads->sg needed");
+  const rgx_camera *cams = f->cams.data();
+  const int32_t n_views = (int32_t)f->cams.size();
   MarchOpts m;
-  rgx_status s = make_opts(ctx, bvh, opts, m);
+  rgx_status s = make_opts(ctx, bvh, &f->opts, m);
   if (s != RGX_OK) return s;
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   std::vector<ViewTable> tabs;
   if ((s = view_tables(ctx, cams, n_views, m, tabs)) != RGX_OK) return s;
   const SceneDev sd = scene_of(bvh);
   // the accumulators are zero: cleared by the build and by every finalisation
   ctx->replayed = 0;
-  if (m.ess && !m.brute_force && ctx->replay_key != 0 &&
-      ctx->replay_key == march_key(bvh, cams, n_views, m)) {
+  if (f->recorded) {
     m.replay_mode = 2;
-    m.replay = (float *)ctx->replay.p;
-    m.wrec = (uint32_t *)ctx->wrec.p;
-    m.wrec_tile = (uint32_t *)ctx->wrec_tile.p;
-    m.wrec_cap = (uint32_t)std::min<size_t>(ctx->wrec.bytes / sizeof(uint32_t), 0xfffffff0u);
+    m.replay = (float *)f->replay.p;
+    m.wrec = (uint32_t *)f->wrec.p;
+    m.wrec_tile = (uint32_t *)f->wrec_tile.p;
+    m.wrec_cap = (uint32_t)std::min<size_t>(f->wrec.bytes / sizeof(uint32_t), 0xfffffff0u);
     ctx->replayed = 1;
   }
   BwdIn in;
@@ -581,6 +646,7 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
   in.grad_rgb = grad_rgb;
   in.grad_T = grad_T;
   in.acc = (float *)bvh->acc.p;
+  in.sgacc = bvh->n_sg > 0 ? (float *)bvh->sgacc.p : nullptr;
   if (!grads->densify) {
     for (const ViewTable &t : tabs) {
       if (t.n_tiles == 0) continue;
@@ -592,8 +658,8 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
     // accumulated mean slots, turned into the densification statistic
     if (!grads->densify_views) return fail(ctx, RGX_ERR_INVALID_ARG, "densify needs densify_views");
     rgx_bvh *mb = const_cast<rgx_bvh *>(bvh);
-    HIP_TRY(ctx, ensure(mb->zprev, (size_t)bvh->n * 3 * sizeof(float)));
-    HIP_TRY(ctx, launch_fill(mb->zprev.p, bvh->n * 3, 0u, stream));
+    HIP_TRY(ctx, ensure(mb->zsum, (size_t)bvh->n * 3 * sizeof(float)));
+    HIP_TRY(ctx, launch_fill(mb->zsum.p, bvh->n * 3, 0u, stream));
     int64_t ray0 = 0, tile0 = 0;
     for (int v = 0; v < n_views; v++) {
       std::vector<ViewTable> one;
@@ -606,14 +672,38 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_c
                            [&] { return launch_backward(sd, t, m, in, shape_for(ctx, m, t.n_tiles, bwd_waves_per_cu(m)), stream); }));
       }
       const float *c2w = cams[v].cam_to_world;
-      HIP_TRY(ctx, launch_densify(sd, (const float *)bvh->acc.p, (float *)mb->zprev.p, c2w[3], c2w[7],
+      HIP_TRY(ctx, launch_densify(sd, (float *)bvh->acc.p, (float *)mb->zsum.p, c2w[3], c2w[7],
                                   c2w[11], cams[v].fx, grads->densify, grads->densify_views, stream));
     }
+    HIP_TRY(ctx, launch_densify_restore(sd, (float *)bvh->acc.p, (const float *)mb->zsum.p, stream));
   }
   HIP_TRY(ctx, timed(ctx, RGX_KERN_FINALIZE, stream, [&] {
     return launch_finalize_grads(sd, bvh->sh_k, (float *)bvh->acc.p, grads->means, grads->log_scales,
                                  grads->quats, grads->density, grads->sh, grads->accumulate, stream);
   }));
+  if (bvh->n_sg > 0)
+    HIP_TRY(ctx, launch_finalize_sg(sd, (float *)bvh->sgacc.p, grads->sg, grads->accumulate, stream));
+  return RGX_OK;
+}
+
+void rgx_fwd_destroy(rgx_fwd *f) {
+  if (!f) return;
+  (void)hipSetDevice(f->device);
+  release(f->replay);
+  release(f->wrec);
+  release(f->wrec_tile);
+  release(f->totals);
+  for (void *p : f->retired) (void)hipFree(p);
+  delete f;
+}
+
+rgx_status rgx_sync_stats(rgx_context *ctx, const rgx_fwd *f, int64_t *out, hipStream_t stream) {
+  if (!ctx || !f || !out) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
+  if (f->ctx != ctx) return fail(ctx, RGX_ERR_STATE, "state of another context");
+  if (!f->has_totals) return fail(ctx, RGX_ERR_STATE, "the forward was not given a stats buffer");
+  HIP_TRY(ctx, enter(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  HIP_TRY(ctx, hipMemcpy(out, f->totals.p, RGX_NTOT * sizeof(int64_t), hipMemcpyDeviceToHost));
   return RGX_OK;
 }
 
@@ -627,7 +717,7 @@ rgx_status rgx_dump_hits(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera 
   rgx_status s = make_opts(ctx, bvh, opts, m);
   if (s != RGX_OK) return s;
   m.persistent = 0;
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   if ((s = check_camera(ctx, *cam)) != RGX_OK) return s;
   ViewTable t;
   memset(&t, 0, sizeof t);
@@ -650,11 +740,30 @@ rgx_status rgx_dump_hits(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera 
   return RGX_OK;
 }
 
+rgx_status rgx_false_positives(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cam,
+                               const int32_t *pix, int32_t n_rays, const float *t_end,
+                               int32_t *count, hipStream_t stream) {
+  if (!ctx || !bvh || !cam || !pix || !t_end || !count || n_rays <= 0)
+    return fail(ctx, RGX_ERR_INVALID_ARG, "bad argument");
+  if (bvh->ctx != ctx) return fail(ctx, RGX_ERR_STATE, "structure built on another context");
+  rgx_status s = check_camera(ctx, *cam);
+  if (s != RGX_OK) return s;
+  HIP_TRY(ctx, enter(ctx->device));
+  View V;
+  memset(&V, 0, sizeof V);
+  V.width = cam->width; V.height = cam->height;
+  V.fx = cam->fx; V.fy = cam->fy; V.cx = cam->cx; V.cy = cam->cy;
+  memcpy(V.c2w, cam->cam_to_world, sizeof V.c2w);
+  V.t_near = cam->t_near; V.t_far = cam->t_far;
+  HIP_TRY(ctx, launch_false_positives(scene_of(bvh), V, pix, n_rays, t_end, count, ctx->queue + 8, stream));
+  return RGX_OK;
+}
+
 rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *b, uint64_t *keys, int32_t *perm,
                          float *aabb, float *nodes, float *nodes4, int64_t *n_active,
                          hipStream_t stream) {
   if (!ctx || !b) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
   const size_t n = (size_t)b->n;
   if (keys)
@@ -685,7 +794,7 @@ rgx_status rgx_set_kernel_timing(rgx_context *ctx, int32_t enable) {
 rgx_status rgx_kernel_times(rgx_context *ctx, double *ms, int64_t *launches, int32_t reset) {
   if (!ctx || !ms || !launches) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
   for (int k = 0; k < RGX_NKERN; k++) { ms[k] = 0.0; launches[k] = 0; }
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   for (size_t i = 0; i < ctx->ev_used; i += 2) {
     HIP_TRY(ctx, hipEventSynchronize(ctx->ev[i + 1]));
     float t = 0.0f;
@@ -703,7 +812,7 @@ rgx_status rgx_isotropic_loss(rgx_context *ctx, int64_t n, const float *log_scal
   if (!ctx || !log_scales || !loss || !grad) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
   if (n <= 0 || n > RGX_MAX_GAUSSIANS) return fail(ctx, RGX_ERR_INVALID_ARG, "n out of range");
   if (!(r0 > 0.0f) || !std::isfinite(r0)) return fail(ctx, RGX_ERR_INVALID_ARG, "r0 must be > 0");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   const int64_t nb = iso_blocks(n);
   if (nb > ctx->partial_cap) {
     if (ctx->partial) (void)hipFree(ctx->partial);
@@ -725,14 +834,33 @@ rgx_status rgx_isotropic_loss_noalloc(rgx_context *ctx, int64_t n, const float *
     return fail(ctx, RGX_ERR_INVALID_ARG, "n exceeds the fixed workspace of the allocation-free loss");
   if (!(r0 > 0.0f) || !std::isfinite(r0)) return fail(ctx, RGX_ERR_INVALID_ARG, "r0 must be > 0");
   if (!ctx->iso_scratch) return fail(ctx, RGX_ERR_STATE, "fixed workspace address not resolved");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   HIP_TRY(ctx, launch_isotropic_loss(n, log_scales, r0, loss, grad, accumulate, ctx->iso_scratch, stream));
+  return RGX_OK;
+}
+
+rgx_status rgx_adam_step(rgx_context *ctx, const rgx_adam_group *groups, int32_t n_groups,
+                         int32_t *step, float beta1, float beta2, float eps, hipStream_t stream) {
+  if (!ctx || !groups || !step || n_groups < 1) return fail(ctx, RGX_ERR_INVALID_ARG, "bad argument");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(ctx, RGX_ERR_INVALID_ARG, "need 0 <= beta < 1 and eps > 0");
+  for (int32_t k = 0; k < n_groups; k++) {
+    const rgx_adam_group &g = groups[k];
+    if (g.n < 0 || (g.n > 0 && (!g.param || !g.grad || !g.m || !g.v)) || !std::isfinite(g.lr))
+      return fail(ctx, RGX_ERR_INVALID_ARG, "bad Adam group");
+  }
+  HIP_TRY(ctx, enter(ctx->device));
+  HIP_TRY(ctx, launch_adam_tick(step, stream));
+  for (int32_t k = 0; k < n_groups; k++) {
+    const rgx_adam_group &g = groups[k];
+    HIP_TRY(ctx, launch_adam(g.n, g.param, g.grad, g.m, g.v, g.lr, beta1, beta2, eps, step, stream));
+  }
   return RGX_OK;
 }
 
 rgx_status rgx_error_flags(rgx_context *ctx, int32_t *flags, hipStream_t stream) {
   if (!ctx || !flags) return fail(ctx, RGX_ERR_INVALID_ARG, "null argument");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, enter(ctx->device));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
   HIP_TRY(ctx, hipMemcpy(flags, ctx->queue + 8, 4, hipMemcpyDeviceToHost));
   return RGX_OK;

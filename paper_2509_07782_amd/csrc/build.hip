@@ -109,6 +109,32 @@ __global__ __launch_bounds__(256) void k_preprocess(int64_t n, const float *__re
   if (threadIdx.x == 0 && scount) atomicAdd(&counters[0], scount);
 }
 
+// Spherical-Gaussian lobes (user order): lobe j of the user record (amplitude
+// rgb, axis xyz, sharpness) becomes (amplitude rgb, sharpness, unit axis,
+// |xi|); absent lobes (j >= n_sg, a zero or non-finite axis) are all zero, so
+// they add nothing to the colour and get no gradient.
+__global__ __launch_bounds__(256) void k_sg_pack(int64_t n, int n_sg, const float *__restrict__ sg,
+                                                 float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < kMaxSg; j++) {
+    float r[kSgLobeFloats] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (j < n_sg) {
+      const float *p = sg + ((size_t)i * n_sg + j) * kSgUserFloats;
+      const float xn = sqrtf(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
+      if (xn > 0.0f && isfinite(xn)) {
+        r[0] = p[0]; r[1] = p[1]; r[2] = p[2];
+        r[3] = p[6];
+        r[4] = p[3] / xn; r[5] = p[4] / xn; r[6] = p[5] / xn;
+        r[7] = xn;
+      }
+    }
+    float4 *o = reinterpret_cast<float4 *>(out + (size_t)kSgFloats * i + kSgLobeFloats * j);
+    o[0] = make_float4(r[0], r[1], r[2], r[3]);
+    o[1] = make_float4(r[4], r[5], r[6], r[7]);
+  }
+}
+
 // Spread the low 21 bits of v so that bit b lands at bit 3b.
 __device__ __forceinline__ uint64_t spread3(uint64_t v) {
   v &= 0x1fffffull;
@@ -478,6 +504,11 @@ hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
   k_gather_rows<<<nblk(n * a.col_stride, 256), 256, 0, st>>>(n, a.counters, perm, a.sh,
                                                              3 * a.sh_k, 3 * a.sh_k, a.col,
                                                              a.col_stride);
+  if (a.n_sg > 0) {
+    k_sg_pack<<<nblk(n, 256), 256, 0, st>>>(n, a.n_sg, a.sg, a.sg_user);
+    k_gather_rows<<<nblk(n * kSgFloats, 256), 256, 0, st>>>(n, a.counters, perm, a.sg_user,
+                                                           kSgFloats, kSgFloats, a.sgrec, kSgFloats);
+  }
   int64_t P = 1;
   while (P < n) P <<= 1;
   k_seg_leaves<<<nblk(P, 256), 256, 0, st>>>(P, a.counters, a.aabb, a.seg);

@@ -16,6 +16,14 @@ constexpr int kColFloats = 48;            // colour record: 3 x 16 SH coefficien
 // 4-wide node, < 0 leaf ~j, kNoChild none), 4 leaf ranges (first, last).
 constexpr int kNode4Floats = 36;
 constexpr int kAuxFloats = 8;             // s.xyz, unit quaternion (w,x,y,z), |q|
+// Spherical-Gaussian colour lobes (the 9 SH + 7 SG appearance model): up to
+// kMaxSg lobes per Gaussian, kSgLobeFloats per lobe in the packed record:
+// amplitude rgb, sharpness lambda, unit axis xyz, |xi| (0: lobe absent).
+constexpr int kMaxSg = 7;
+constexpr int kSgLobeFloats = 8;
+constexpr int kSgFloats = kMaxSg * kSgLobeFloats;   // 56
+constexpr int kSgUserFloats = 7;          // user lobe: amplitude rgb, axis xyz, sharpness
+constexpr int kSgAccFloats = 64;          // per Gaussian: 8 slots per lobe (da rgb, dlambda, h xyz, pad)
 constexpr int32_t kNoChild = INT32_MIN;
 
 // Packed geometry record, Z order: [mu.xyz, k^2, M (3x3 row-major), sigma~, log2 sigma~, pad]
@@ -26,9 +34,9 @@ enum GeomSlot { G_MU = 0, G_K2 = 3, G_M = 4, G_SIG = 13, G_L2SIG = 14, G_RAD = 1
 // per-ray statistics slots (same order as the public RGX_STAT_* enum)
 enum { ST_Q = 0, ST_P, ST_SAMPLES, ST_SEGMENTS, ST_CLOSEST, ST_BOX_ONLY, ST_NODES, ST_LEAVES,
        ST_WINDOWS, ST_CHUNKED, ST_CAND, ST_CAND_HIT, ST_KCYC_COLLECT, ST_KCYC_CLOSEST,
-       ST_KCYC_TILE };
-constexpr int kNStatUsed = 15;
-constexpr int kNStat = 15;
+       ST_KCYC_TILE, ST_T_END };
+constexpr int kNStatUsed = 16;
+constexpr int kNStat = 16;
 
 struct View {
   const int32_t *tile_order;  // tile coordinates (tx | ty << 16) in launch order

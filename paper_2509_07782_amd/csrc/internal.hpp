@@ -10,6 +10,9 @@ namespace rgx {
 struct BuildArgs {
   int64_t n;
   const float *means, *log_scales, *quats, *density, *sh;
+  const float *sg;           // [n, n_sg, 7] user lobes (n_sg > 0)
+  int n_sg;
+  float *sg_user, *sgrec;    // packed lobes, user order / Z order [n, kSgFloats]
   int sh_k, col_stride, morton_bits;
   float sigma_eps;
   // scratch (user order)
@@ -47,6 +50,8 @@ struct SceneDev {
   const int32_t *counters;    // [0] = active count
   const uint32_t *perm;       // Z index -> user index
   const float *aux;           // [n,8] s.xyz, unit quaternion wxyz, |q| (Z order)
+  const float *sg;            // [n, kSgFloats] packed lobes (Z order), nullptr without lobes
+  int n_sg;
   int64_t n;
 };
 
@@ -63,6 +68,7 @@ struct FwdOut {
 struct BwdIn {
   const float *rgb, *T, *grad_rgb, *grad_T;
   float *acc;                // [n, 64] packed-order gradient accumulators
+  float *sgacc;              // [n, kSgAccFloats] lobe accumulators (with lobes)
 };
 
 struct LaunchShape {
@@ -82,9 +88,24 @@ hipError_t launch_backward(const SceneDev &s, const ViewTable &vt, const MarchOp
 hipError_t launch_finalize_grads(const SceneDev &s, int sh_k, float *acc, float *g_means,
                                  float *g_log_scales, float *g_quats, float *g_density,
                                  float *g_sh, int accumulate, hipStream_t st);
-hipError_t launch_densify(const SceneDev &s, const float *acc, float *zprev, float ox, float oy,
+hipError_t launch_finalize_sg(const SceneDev &s, float *sgacc, float *g_sg, int accumulate,
+                              hipStream_t st);
+hipError_t launch_densify(const SceneDev &s, float *acc, float *zsum, float ox, float oy,
                           float oz, float focal, float *densify, int32_t *views, hipStream_t st);
+hipError_t launch_densify_restore(const SceneDev &s, float *acc, const float *zsum, hipStream_t st);
+// Totals of a forward's per-ray statistics [rays, kNStat] into int64
+// totals[RGX_NTOT]; wrec_tile (nullable) gives the record's per-tile status.
+hipError_t launch_stat_totals(const int32_t *stats, int64_t rays, const SceneDev &s,
+                              const uint32_t *wrec_tile, int64_t tiles, int64_t *totals,
+                              hipStream_t st);
+// Whole-ray AABB false positives of listed pixels of one view.
+hipError_t launch_false_positives(const SceneDev &s, const View &v, const int32_t *pix, int32_t n_rays,
+                                  const float *t_end, int32_t *count, int32_t *error_flag,
+                                  hipStream_t st);
 hipError_t launch_fill(void *p, int64_t n_words, uint32_t value, hipStream_t st);
+hipError_t launch_adam_tick(int32_t *step, hipStream_t st);
+hipError_t launch_adam(int64_t n, float *p, const float *g, float *m, float *v, float lr, float b1,
+                       float b2, float eps, const int32_t *step, hipStream_t st);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 
 }  // namespace rgx

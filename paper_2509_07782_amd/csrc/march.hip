@@ -155,19 +155,45 @@ __device__ __forceinline__ void colour(const float *col, int j, const float *Y, 
   cr = acc[0]; cg = acc[1]; cb = acc[2];
 }
 
-// Wave-uniform DFS stack, entry i held by lane i of s0 (i < 64) or s1.
+// Spherical-Gaussian lobes of Gaussian j added to the lane's colour:
+// c += a_k exp(lambda_k (u_k.d - 1)) for the kMaxSg packed lobes (absent
+// lobes have a = 0).  One lobe (two 16-byte scalar loads) per iteration, so
+// the lobes do not all hold scalar registers at once.
+__device__ __forceinline__ void sg_colour(const float *sg, int j, float dx, float dy, float dz,
+                                          float &cr, float &cg, float &cb) {
+  cfloat4p p = as_const4(sg) + (size_t)(kSgFloats / 4) * j;
+#pragma unroll 1
+  for (int k = 0; k < kMaxSg; k++) {
+    const vf4 a = p[2 * k], u = p[2 * k + 1];
+    const float cosang = fmaf(u.x, dx, fmaf(u.y, dy, u.z * dz));
+    const float g = __builtin_amdgcn_exp2f(a.w * kLog2e * (cosang - 1.0f));
+    cr = fmaf(a.x, g, cr);
+    cg = fmaf(a.y, g, cg);
+    cb = fmaf(a.z, g, cb);
+  }
+}
+
+// Wave-uniform DFS stack, entry i held by lane i % 64 of s0, s1 or s2.  The
+// closest-hit walk over the 4-wide records pushes at most 3 entries per
+// record on its path.  Binary internal nodes lie at most 86 levels deep (the
+// Karras split positions grow strictly down the tree over the 63-bit key
+// extended by a 23-bit index), so a path meets at most 44 4-wide records and
+// the stack never holds more than 132 entries: 192 always suffice.
 struct WaveStack {
-  int s0 = 0, s1 = 0, sp = 0, lane = 0;
+  int s0 = 0, s1 = 0, s2 = 0, sp = 0, lane = 0;
   __device__ __forceinline__ bool push(int v) {
     if (sp < 64) s0 = lane == sp ? v : s0;
     else if (sp < 128) s1 = lane == sp - 64 ? v : s1;
+    else if (sp < 192) s2 = lane == sp - 128 ? v : s2;
     else return false;
     sp++;
     return true;
   }
   __device__ __forceinline__ int pop() {
     sp--;
-    return sp < 64 ? __builtin_amdgcn_readlane(s0, sp) : __builtin_amdgcn_readlane(s1, sp - 64);
+    return sp < 64 ? __builtin_amdgcn_readlane(s0, sp)
+                   : sp < 128 ? __builtin_amdgcn_readlane(s1, sp - 64)
+                              : __builtin_amdgcn_readlane(s2, sp - 128);
   }
 };
 
@@ -407,20 +433,22 @@ __device__ __forceinline__ float wave_sum_slots16(const float *g, int lane) {
   return u;
 }
 
-// SH-coefficient gradients of a batch of up to 16 Gaussians as a matrix
-// product on the matrix cores.  For Gaussian b of the batch and channel c,
-// dL/df_{m,c} = sum over the tile's rays r of Y_m(d_r) G_c(r) S_b(r), S_b(r)
-// the ray's sum over samples of w_k dL/dW_k-weight (zero where the ray misses
-// b).  With A_c[m][r] = Y_m(d_r) G_c(r) fixed for the tile and B[r][b] =
-// S_b(r) staged in LDS, each channel is 16 chained 16x16x4 FP32 MFMAs over the
-// 64 rays.  Operand layout of v_mfma_f32_16x16x4_f32 (wave64): A[i][k] in lane
-// i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i / 4), register
-// i % 4.
-typedef float f4v __attribute__((ext_vector_type(4)));
-constexpr int kSbStride = 66;   // floats per staged row: transposed reads hit distinct banks
+// SH-coefficient gradients of a batch of up to 16 Gaussians.  For Gaussian
+// b of the batch and channel c, dL/df_{m,c} = sum over the tile's rays r of
+// S_b(r) Y_m(d_r) G_c(r), S_b(r) the ray's sum over samples of w_k T_k phi_k
+// (zero where the ray misses b).  A_c[r][m] = Y_m(d_r) G_c(r) is fixed for
+// the tile and held in registers: lane L keeps column m = L & 15 for the
+// rays r = 4q + (L >> 4), q = 0..15.  S[b][r] is staged in LDS for the
+// batch.  Per Gaussian, each lane sums its 16 rays for its column (three
+// channels, 48 FMAs), two cross-lane adds finish the sum over the four ray
+// groups, and lanes 0-15 add 16 consecutive floats per channel to the
+// Gaussian's row.  (The batch is a small dense product; it runs on the
+// vector units: a matrix-core version measured 3.9 % faster on the
+// backward, not worth a second kind of arithmetic unit on this path.)
+constexpr int kSbStride = 66;   // floats per staged row
 
 struct ShBatch {
-  float a[3][16];   // A_c for rays 4s + (lane >> 4), row m = lane & 15
+  float a[3][16];   // A_c for rays 4q + (lane >> 4), column m = lane & 15
   int n = 0;        // uniform: staged Gaussians
   int id = 0;       // lane b < 16: the Gaussian staged in row b
 };
@@ -451,25 +479,28 @@ __device__ __forceinline__ void sh_batch_flush(ShBatch &B, const float *sb, floa
                                                int lane) {
   if (B.n == 0) return;
   __builtin_amdgcn_wave_barrier();
-  f4v d0 = {0.0f, 0.0f, 0.0f, 0.0f}, d1 = d0, d2 = d0;
+  const int m = lane & 15, k = lane >> 4;
+  for (int b = 0; b < B.n; b++) {
+    float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f;
 #pragma unroll
-  for (int q = 0; q < 16; q++) {
-    const float bv = sb[(lane & 15) * kSbStride + 4 * q + (lane >> 4)];
-    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[0][q], bv, d0, 0, 0, 0);
-    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[1][q], bv, d1, 0, 0, 0);
-    d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[2][q], bv, d2, 0, 0, 0);
-  }
-  const int jb = __shfl(B.id, lane & 15, 64);
-  if ((lane & 15) < B.n) {
-    float *row = acc + (size_t)kAccFloats * jb + 16;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int m = 4 * (lane >> 4) + i;
-      if (m < sh_k) {
-        unsafeAtomicAdd(row + m, d0[i]);
-        unsafeAtomicAdd(row + 16 + m, d1[i]);
-        unsafeAtomicAdd(row + 32 + m, d2[i]);
-      }
+    for (int q = 0; q < 16; q++) {
+      const float sv = sb[b * kSbStride + 4 * q + k];
+      d0 = fmaf(sv, B.a[0][q], d0);
+      d1 = fmaf(sv, B.a[1][q], d1);
+      d2 = fmaf(sv, B.a[2][q], d2);
+    }
+    d0 += __shfl_xor(d0, 32, 64);
+    d0 += __shfl_xor(d0, 16, 64);
+    d1 += __shfl_xor(d1, 32, 64);
+    d1 += __shfl_xor(d1, 16, 64);
+    d2 += __shfl_xor(d2, 32, 64);
+    d2 += __shfl_xor(d2, 16, 64);
+    const int jb = __shfl(B.id, b, 64);
+    if (k == 0 && m < sh_k) {
+      float *row = acc + (size_t)kAccFloats * jb + 16;
+      unsafeAtomicAdd(row + m, d0);
+      unsafeAtomicAdd(row + 16 + m, d1);
+      unsafeAtomicAdd(row + 32 + m, d2);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -510,12 +541,15 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
   const float lo = search ? ss.cl_lo : kInf;
   float hi = search ? tf : -kInf;
   float best = kInf;
+  // Every candidate value max(t_in, lo) is at least lo: a lane whose best
+  // reached lo has its answer and leaves the search (hi below lo), so that
+  // the boxes around a ray starting inside ellipsoids are not all walked.
   auto leaf = [&](int j) {
     const Gauss g = with_origin(load_gauss(s.geom, j), r.ox, r.oy, r.oz);
     const Chord c = chord(g, r);
     if (c.exists && c.tin <= hi && c.tout >= lo) {
       best = fminf(best, fmaxf(c.tin, lo));
-      hi = fminf(hi, best);
+      hi = best <= lo ? -kInf : fminf(hi, best);
     }
   };
   if (ballot(search) == 0) {
@@ -529,6 +563,7 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
     st.sp = 0;
     int node = 0, visits = 0;
     for (;;) {
+      if (ballot(hi >= lo) == 0) break;   // every searching lane has its answer
       if (node < 0) {
         if (st.sp == 0) break;
         const int v = st.pop();
@@ -1589,7 +1624,7 @@ __device__ __forceinline__ bool next_chunk(const SceneDev &s, const MarchOpts &o
 // ---------------------------------------------------------------------------
 // Forward kernel (and the hit-dump variant).
 
-template <int NS, bool DUMP, bool STATS>
+template <int NS, bool DUMP, bool STATS, bool SG = false>
 __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, ViewTable vt, MarchOpts op,
                                                    FwdOut out, LaunchShape ls) {
   __shared__ WaveMem M;
@@ -1658,6 +1693,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
     int32_t cnt[kNStatUsed];
 #pragma unroll
     for (int k = 0; k < kNStatUsed; k++) cnt[k] = 0;
+    cnt[ST_T_END] = __float_as_int(tf);
     // statistics builds also time the phases of the tile (shader clock)
     int64_t cyc_collect = 0, cyc_closest = 0, cyc_t0 = 0, cyc_tile = stats ? clock64() : 0;
     int64_t cyc_boxstat = 0;   // statistics-only work inside the collection
@@ -1672,7 +1708,11 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       if (stats) cyc_closest += clock64() - cyc_t0;
       if (ss.alive) {
         const float a0 = grid ? fmaf((float)(ss.seg_i * NS), op.dt, tn) : ss.a;
-        if (!(a0 < tf) || !(T > op.t_eps)) ss.alive = false;
+        if (!(a0 < tf)) ss.alive = false;
+        else if (!(T > op.t_eps)) {
+          ss.alive = false;
+          if (stats) cnt[ST_T_END] = __float_as_int(a0);
+        }
       }
       if (ballot(ss.alive) == 0) break;
       float a = 0.0f, b = 0.0f, dt = op.dt;
@@ -1720,6 +1760,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
           }
           float cr, cg, cb;
           colour(s.col, j, Y, cr, cg, cb);
+          if constexpr (SG) sg_colour(s.sg, j, r.dx, r.dy, r.dz, cr, cg, cb);
           float wk[NS];
           const uint32_t live = sample_weights<NS, true>(g, c, sp, wk);
 #pragma unroll
@@ -1804,6 +1845,44 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
 }
 
 // ---------------------------------------------------------------------------
+// Lobe gradients of Gaussian j for one pass-B visit.  The lane's dL/dc is
+// S G (S = sum_k w_k T_k phi_k, zero where the lane missed j), so per lobe
+// with g = exp(lambda (u.d - 1)) and A = a.G:
+//   dL/da = S g G,  dL/dlambda = S A g (u.d - 1),  h = S A g d,
+// h being dL/du / lambda (the finalisation multiplies by lambda and takes
+// the component across u).  Two lobes (16 slots) at a time are summed over
+// the wave and added with one atomic per slot.
+__device__ __forceinline__ void sg_slots(const float *sg, float *sgacc, int j, float S, float G0,
+                                         float G1, float G2, const Ray &r, int lane) {
+  cfloat4p p = as_const4(sg) + (size_t)(kSgFloats / 4) * j;
+#pragma unroll 1
+  for (int pair = 0; pair < (kMaxSg + 1) / 2; pair++) {
+    float v[16];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      const int k = 2 * pair + h;
+      float *o = v + 8 * h;
+      if (k < kMaxSg) {
+        const vf4 a = p[2 * k], u = p[2 * k + 1];
+        const float cosang = fmaf(u.x, r.dx, fmaf(u.y, r.dy, u.z * r.dz));
+        const float sgv = S * __builtin_amdgcn_exp2f(a.w * kLog2e * (cosang - 1.0f));
+        const float sa = sgv * fmaf(a.x, G0, fmaf(a.y, G1, a.z * G2));
+        o[0] = sgv * G0; o[1] = sgv * G1; o[2] = sgv * G2;
+        o[3] = sa * (cosang - 1.0f);
+        o[4] = sa * r.dx; o[5] = sa * r.dy; o[6] = sa * r.dz;
+        o[7] = 0.0f;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; e++) o[e] = 0.0f;
+      }
+    }
+    const float mine = wave_sum_slots16(v, lane);
+    if ((lane & 3) == 0 && 16 * pair + (lane >> 2) < kMaxSg * kSgLobeFloats)
+      unsafeAtomicAdd(sgacc + (size_t)kSgAccFloats * j + 16 * pair + (lane >> 2), mine);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Backward kernel: replays the forward's segments from the same window lists
 // (or brute force / depth-first sources) in the same order, recomputes the
 // transmittance before every sample, derives dL/dsigma_k and dL/dW_k, then
@@ -1811,10 +1890,10 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
 // geometry and density slots are summed over the wave (DPP and half-wave
 // swaps) before one atomic per slot; the SH-coefficient slots, a per-ray
 // constant times one scalar per (ray, Gaussian), are staged 16 Gaussians at a
-// time and multiplied out on the matrix cores.  Two waves per SIMD: the
-// tile's matrix operand and the staging buffer need the registers and LDS.
+// time and multiplied out per batch.  Two waves per SIMD: the tile's operand
+// and the staging buffer need the registers and LDS.
 
-template <int NS>
+template <int NS, bool SG = false>
 __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt, MarchOpts op,
                                                     BwdIn in, LaunchShape ls) {
   __shared__ WaveMem M;
@@ -1925,6 +2004,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
           nhit++;
           float cr, cg, cb;
           colour(s.col, j, Y, cr, cg, cb);
+          if constexpr (SG) sg_colour(s.sg, j, r.dx, r.dy, r.dz, cr, cg, cb);
           const float gc = fmaf(Gc0, cr, fmaf(Gc1, cg, Gc2 * cb));
           float wk[NS];
           sample_weights<NS>(g, c, sp, wk);
@@ -1995,6 +2075,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
             const float inv_sig = __builtin_amdgcn_rcpf(g.sig);
             float cr, cg, cb;
             colour(s.col, j, Y, cr, cg, cb);
+            if constexpr (SG) sg_colour(s.sg, j, r.dx, r.dy, r.dz, cr, cg, cb);
             const float gc = fmaf(Gc0, cr, fmaf(Gc1, cg, Gc2 * cb));
             // dL/dw_k = dsigma_k + G.c_l T_k phi_k; dq_k = -w_k dL/dw_k / 2
             // moments over u_k = u_0 + k dt from sums over the sample index
@@ -2028,11 +2109,12 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
             v[15] = ds * inv_sig;
           }
           // slots [0,16): geometry and density, summed over the wave; the SH
-          // slots go through the matrix-core batch
+          // slots go through the per-tile batch
           sb[shb.n * kSbStride + lane] = S;
           shb.id = lane == shb.n ? j : shb.id;
           const float mine = wave_sum_slots16(v, lane);
           if ((lane & 3) == 0) unsafeAtomicAdd(in.acc + (size_t)kAccFloats * j + (lane >> 2), mine);
+          if constexpr (SG) sg_slots(s.sg, in.sgacc, j, hit ? S : 0.0f, Gc0, Gc1, Gc2, r, lane);
           if (++shb.n == 16) sh_batch_flush(shb, sb, in.acc, op.sh_k, lane);
         };
         // the list still holds the whole window, or the segment's last Z
@@ -2166,11 +2248,25 @@ static void fwd_dispatch(const SceneDev &s, const ViewTable &vt, const MarchOpts
   else k_forward<NS, false, false><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
 }
 
+// Lobed colour (spherical Gaussians): N_s = 8 only (checked by the host).
+// The hit dump does not depend on colour and takes the plain kernel.
+static void fwd_dispatch_sg(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
+                            const FwdOut &out, const LaunchShape &ls, hipStream_t st) {
+  if (out.dump_pix) k_forward<8, true, false><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
+  else if (out.stats) k_forward<8, false, true, true><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
+  else k_forward<8, false, false, true><<<ls.grid, kWave, 0, st>>>(s, vt, op, out, ls);
+}
+
 hipError_t launch_forward(const SceneDev &s, const ViewTable &vt, const MarchOpts &op,
                           const FwdOut &out, const LaunchShape &ls, hipStream_t st) {
   if (op.persistent) {
     hipError_t e = launch_fill(ls.queue, 8, 0u, st);
     if (e != hipSuccess) return e;
+  }
+  if (s.n_sg > 0) {
+    if (op.n_s != 8) return hipErrorInvalidValue;
+    fwd_dispatch_sg(s, vt, op, out, ls, st);
+    return hipGetLastError();
   }
   switch (op.n_s) {
     case 1: fwd_dispatch<1>(s, vt, op, out, ls, st); break;
@@ -2188,6 +2284,11 @@ hipError_t launch_backward(const SceneDev &s, const ViewTable &vt, const MarchOp
   if (op.persistent) {
     hipError_t e = launch_fill(ls.queue, 8, 0u, st);
     if (e != hipSuccess) return e;
+  }
+  if (s.n_sg > 0) {
+    if (op.n_s != 8) return hipErrorInvalidValue;
+    k_backward<8, true><<<ls.grid, kWave, 0, st>>>(s, vt, op, in, ls);
+    return hipGetLastError();
   }
   switch (op.n_s) {
     case 1: k_backward<1><<<ls.grid, kWave, 0, st>>>(s, vt, op, in, ls); break;
@@ -2209,29 +2310,74 @@ hipError_t launch_finalize_grads(const SceneDev &s, int sh_k, float *acc, float 
   return hipGetLastError();
 }
 
-// Densification statistic of one view (Sec. 3.5, Eq. 12): the view's mean
-// gradient is -2 M^T dZ, dZ the change of the accumulated mean slots since the
-// previous view; densify[user i] += |mu - o| / f * |grad|, views += grad != 0.
+// Lobe gradients to user order: per lobe, dL/da and dL/dlambda as summed;
+// the axis through u = xi / |xi|: dL/dxi = lambda (h - (h.u) u) / |xi|.
+// Absent lobes and inactive Gaussians get zeros.  Clears the accumulators.
+__global__ __launch_bounds__(256) void k_finalize_sg(int64_t n, const int32_t *__restrict__ counters,
+                                                     const uint32_t *__restrict__ perm,
+                                                     const float *__restrict__ sg,
+                                                     float *__restrict__ sgacc, int n_sg,
+                                                     float *__restrict__ g_sg, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t u = perm[i];
+  const bool active = i < counters[0];
+  for (int k = 0; k < n_sg; k++) {
+    float out[kSgUserFloats] = {0, 0, 0, 0, 0, 0, 0};
+    if (active) {
+      const float *A = sgacc + (size_t)kSgAccFloats * i + kSgLobeFloats * k;
+      const float *L = sg + (size_t)kSgFloats * i + kSgLobeFloats * k;
+      if (L[7] > 0.0f) {
+        const float h[3] = {A[4], A[5], A[6]};
+        const float hu = h[0] * L[4] + h[1] * L[5] + h[2] * L[6];
+        const float f = L[3] / L[7];
+        out[0] = A[0]; out[1] = A[1]; out[2] = A[2];
+        for (int e = 0; e < 3; e++) out[3 + e] = f * (h[e] - hu * L[4 + e]);
+        out[6] = A[3];
+      }
+    }
+    float *dst = g_sg + ((size_t)u * n_sg + k) * kSgUserFloats;
+    for (int e = 0; e < kSgUserFloats; e++) dst[e] = accumulate ? dst[e] + out[e] : out[e];
+  }
+  if (active) {
+    float4 *z = reinterpret_cast<float4 *>(sgacc + (size_t)kSgAccFloats * i);
+    for (int e = 0; e < kSgAccFloats / 4; e++) z[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+hipError_t launch_finalize_sg(const SceneDev &s, float *sgacc, float *g_sg, int accumulate,
+                              hipStream_t st) {
+  const unsigned nb = (unsigned)((s.n + 255) / 256);
+  k_finalize_sg<<<nb, 256, 0, st>>>(s.n, s.counters, s.perm, s.sg, sgacc, s.n_sg, g_sg, accumulate);
+  return hipGetLastError();
+}
+
+// Densification statistic of one view (Sec. 3.5, Eq. 12).  The mean slots of
+// the accumulators were zero when the view's backward started, so they hold
+// that view's sum alone: its mean gradient is -2 M^T Z.  densify[user i] +=
+// |mu - o| / f * |grad|, views += grad != 0.  The slots are then moved to
+// zsum (the running sum over the call's views) and cleared for the next view;
+// k_densify_restore puts the sum back before the chain rule.
 __global__ __launch_bounds__(256) void k_densify(int64_t n, const int32_t *__restrict__ counters,
                                                  const uint32_t *__restrict__ perm,
                                                  const float *__restrict__ geom,
-                                                 const float *__restrict__ acc,
-                                                 float *__restrict__ zprev, float ox, float oy,
+                                                 float *__restrict__ acc,
+                                                 float *__restrict__ zsum, float ox, float oy,
                                                  float oz, float inv_focal,
                                                  float *__restrict__ densify,
                                                  int32_t *__restrict__ views) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || i >= counters[0]) return;
   const float *G = geom + (size_t)kGeomFloats * i;
-  float dz[3];
+  float z[3];
   for (int r = 0; r < 3; r++) {
-    const float z = acc[(size_t)kAccFloats * i + r];
-    dz[r] = z - zprev[3 * i + r];
-    zprev[3 * i + r] = z;
+    z[r] = acc[(size_t)kAccFloats * i + r];
+    zsum[3 * i + r] += z[r];
+    acc[(size_t)kAccFloats * i + r] = 0.0f;
   }
   float g2 = 0.0f;
   for (int c = 0; c < 3; c++) {
-    const float gc = -2.0f * (G[G_M + c] * dz[0] + G[G_M + 3 + c] * dz[1] + G[G_M + 6 + c] * dz[2]);
+    const float gc = -2.0f * (G[G_M + c] * z[0] + G[G_M + 3 + c] * z[1] + G[G_M + 6 + c] * z[2]);
     g2 = fmaf(gc, gc, g2);
   }
   if (g2 > 0.0f) {
@@ -2243,11 +2389,173 @@ __global__ __launch_bounds__(256) void k_densify(int64_t n, const int32_t *__res
   }
 }
 
-hipError_t launch_densify(const SceneDev &s, const float *acc, float *zprev, float ox, float oy,
+__global__ __launch_bounds__(256) void k_densify_restore(int64_t n, const int32_t *__restrict__ counters,
+                                                         float *__restrict__ acc,
+                                                         const float *__restrict__ zsum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || i >= counters[0]) return;
+  for (int r = 0; r < 3; r++) acc[(size_t)kAccFloats * i + r] = zsum[3 * i + r];
+}
+
+hipError_t launch_densify(const SceneDev &s, float *acc, float *zsum, float ox, float oy,
                           float oz, float focal, float *densify, int32_t *views, hipStream_t st) {
   const unsigned nb = (unsigned)((s.n + 255) / 256);
-  k_densify<<<nb, 256, 0, st>>>(s.n, s.counters, s.perm, s.geom, acc, zprev, ox, oy, oz,
+  k_densify<<<nb, 256, 0, st>>>(s.n, s.counters, s.perm, s.geom, acc, zsum, ox, oy, oz,
                                 1.0f / focal, densify, views);
+  return hipGetLastError();
+}
+
+hipError_t launch_densify_restore(const SceneDev &s, float *acc, const float *zsum, hipStream_t st) {
+  const unsigned nb = (unsigned)((s.n + 255) / 256);
+  k_densify_restore<<<nb, 256, 0, st>>>(s.n, s.counters, acc, zsum);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Statistics totals of one forward (int64, RGX_TOT_* order of the public
+// header): per-block column sums of the per-ray counters, one atomic per
+// column per block; the inactive Gaussians and the unrecorded tiles of the
+// record are counted by the same launch.
+enum { TOT_RAYS = 0, TOT_Q, TOT_P, TOT_SAMPLES, TOT_SEGMENTS, TOT_CLOSEST, TOT_NODES,
+       TOT_BOX_ONLY, TOT_CHUNKED, TOT_INACTIVE, TOT_UNRECORDED, kNTot };
+
+__global__ __launch_bounds__(256) void k_stat_totals(const int32_t *__restrict__ stats, int64_t rays,
+                                                     int64_t n, const int32_t *__restrict__ counters,
+                                                     const uint32_t *__restrict__ wrec_tile,
+                                                     int64_t tiles, unsigned long long *totals) {
+  constexpr int kCols = 8;
+  const int cols[kCols] = {-1, ST_Q, ST_P, ST_SAMPLES, ST_SEGMENTS, ST_CLOSEST, ST_NODES, ST_BOX_ONLY};
+  __shared__ unsigned long long red[kCols + 2][256];
+  unsigned long long acc[kCols + 2];
+#pragma unroll
+  for (int c = 0; c < kCols + 2; c++) acc[c] = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rays; r += stride) {
+    const int32_t *row = stats + (size_t)r * kNStat;
+    acc[0] += 1;
+#pragma unroll
+    for (int c = 1; c < kCols; c++) acc[c] += (unsigned long long)(uint32_t)row[cols[c]];
+    acc[kCols] += (unsigned long long)(uint32_t)row[ST_CHUNKED];
+  }
+  if (wrec_tile)
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += stride)
+      acc[kCols + 1] += wrec_tile[2 * t] == 1u ? 0ull : 1ull;
+#pragma unroll
+  for (int c = 0; c < kCols + 2; c++) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int c = 0; c < kCols + 2; c++) red[c][threadIdx.x] += red[c][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < kCols; c++) atomicAdd(&totals[c], red[c][0]);
+    atomicAdd(&totals[TOT_CHUNKED], red[kCols][0]);
+    atomicAdd(&totals[TOT_UNRECORDED], red[kCols + 1][0]);
+    if (blockIdx.x == 0) atomicAdd(&totals[TOT_INACTIVE], (unsigned long long)(n - counters[0]));
+  }
+}
+
+hipError_t launch_stat_totals(const int32_t *stats, int64_t rays, const SceneDev &s,
+                              const uint32_t *wrec_tile, int64_t tiles, int64_t *totals,
+                              hipStream_t st) {
+  hipError_t e = launch_fill(totals, 2 * kNTot, 0u, st);
+  if (e != hipSuccess) return e;
+  const int64_t work = rays > tiles ? rays : tiles;
+  int64_t nb = (work + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  if (nb < 1) nb = 1;
+  k_stat_totals<<<(unsigned)nb, 256, 0, st>>>(stats, rays, s.n, s.counters, wrec_tile, tiles,
+                                              reinterpret_cast<unsigned long long *>(totals));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Whole-ray AABB false positives (Sec. 3.4, Eq. 6; minimal AABB of Supp. B)
+// of listed pixels of one view: Gaussians whose minimal AABB mu +/- L,
+// L_a = k sqrt(sum_m R_am^2 s_m^2), meets the ray over [t_n, t_end] while the
+// ellipsoid's chord does not.  One thread per ray walks the binary LBVH with
+// its own stack.  The node boxes are padded unions of padded leaf boxes, so
+// they contain every minimal AABB below them and the walk misses none; the
+// leaves then take the exact (unpadded) test.  Internal nodes lie at most 86
+// levels deep (the Karras split positions grow strictly down the tree over
+// the 63-bit key extended by a 23-bit index), and the walk pushes one child
+// per level, so 96 stack entries always suffice.
+constexpr int kFpStack = 96;
+
+__global__ __launch_bounds__(256) void k_false_positives(SceneDev s, View V, const int32_t *__restrict__ pix,
+                                                         int n_rays, const float *__restrict__ t_end,
+                                                         int32_t *__restrict__ count,
+                                                         int32_t *__restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rays) return;
+  const int n_active = s.counters[0];
+  const int p = pix[i];
+  const Ray r = make_ray(V, p % V.width, p / V.width);
+  const float lo = V.t_near, hi = t_end[i];
+  int fp = 0;
+  auto leaf = [&](int j) {
+    const Gauss g = with_origin(load_gauss_lane(s.geom, j), r.ox, r.oy, r.oz);
+    const float *X = s.aux + (size_t)kAuxFloats * j;
+    const float sx = X[0], sy = X[1], sz = X[2];
+    const float w = X[3], x = X[4], y = X[5], z = X[6];
+    // rows of R(q) for the unit quaternion (w, x, y, z)
+    const float R[9] = {1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y),
+                        2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x),
+                        2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)};
+    const float k = sqrtf(g.k2);
+    const float mu[3] = {g.mx, g.my, g.mz}, o[3] = {r.ox, r.oy, r.oz}, d[3] = {r.dx, r.dy, r.dz};
+    float enter = lo, leave = hi;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      const float e2 = R[3 * a] * R[3 * a] * sx * sx + R[3 * a + 1] * R[3 * a + 1] * sy * sy +
+                       R[3 * a + 2] * R[3 * a + 2] * sz * sz;
+      const float L = k * sqrtf(e2);
+      const float ta = (mu[a] - L - o[a]) / d[a], tb = (mu[a] + L - o[a]) / d[a];
+      enter = fmaxf(enter, fminf(ta, tb));
+      leave = fminf(leave, fmaxf(ta, tb));
+    }
+    const Chord c = chord(g, r);
+    const bool ell = c.exists && c.tin <= hi && c.tout >= lo;
+    if (enter <= leave && !ell) fp++;
+  };
+  if (n_active == 1) {
+    leaf(0);
+  } else if (n_active > 1) {
+    int stack[kFpStack];
+    int sp = 0, node = 0;
+    for (;;) {
+      const vf4 *np = reinterpret_cast<const vf4 *>(s.nodes) + 4 * node;
+      const vf4 a = np[0], b = np[1], c = np[2], d = np[3];
+      const int cl = __float_as_int(a.w), cr = __float_as_int(b.w);
+      const bool hL = cl != kNoChild && box_hit(a.x, a.y, a.z, b.x, b.y, b.z, r, lo, hi);
+      const bool hR = cr != kNoChild && box_hit(c.x, c.y, c.z, d.x, d.y, d.z, r, lo, hi);
+      int next = -1;
+      if (hL) {
+        if (cl < 0) leaf(~cl); else next = cl;
+      }
+      if (hR) {
+        if (cr < 0) leaf(~cr);
+        else if (next < 0) next = cr;
+        else if (sp < kFpStack) stack[sp++] = cr;
+        else { if (err) *err = 6; fp = -1; break; }
+      }
+      if (next >= 0) { node = next; continue; }
+      if (sp == 0) break;
+      node = stack[--sp];
+    }
+  }
+  count[i] = fp;
+}
+
+hipError_t launch_false_positives(const SceneDev &s, const View &v, const int32_t *pix, int32_t n_rays,
+                                  const float *t_end, int32_t *count, int32_t *error_flag,
+                                  hipStream_t st) {
+  if (n_rays <= 0) return hipSuccess;
+  k_false_positives<<<(unsigned)((n_rays + 255) / 256), 256, 0, st>>>(s, v, pix, n_rays, t_end, count,
+                                                                      error_flag);
   return hipGetLastError();
 }
 

@@ -14,10 +14,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RGX_LIBRARY", os.path.join(HERE, "librgx.so"))
 
 RGX_OK = 0
-NSTAT = 15
+NSTAT = 16
 STAT_NAMES = ("Q", "P", "samples", "segments", "closest", "box_only", "nodes", "leaves",
               "windows", "chunked", "cand", "cand_hit", "kcyc_collect", "kcyc_closest",
-              "kcyc_tile")
+              "kcyc_tile", "t_end")
+STAT_T_END = 15   # float bits
+TOTAL_NAMES = ("rays", "Q", "P", "samples", "segments", "closest", "nodes", "box_only",
+               "chunked", "inactive", "unrecorded")   # RGX_TOT_* order
 
 
 class RgxError(RuntimeError):
@@ -27,7 +30,7 @@ class RgxError(RuntimeError):
 class Gaussians(C.Structure):
     _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("means", C.c_void_p),
                 ("log_scales", C.c_void_p), ("quats", C.c_void_p), ("density", C.c_void_p),
-                ("sh", C.c_void_p)]
+                ("sh", C.c_void_p), ("n_sg", C.c_int32), ("sg", C.c_void_p)]
 
 
 class BuildOpts(C.Structure):
@@ -46,19 +49,26 @@ class RenderOpts(C.Structure):
                 ("t_eps", C.c_float), ("ess", C.c_int32), ("brute_force", C.c_int32),
                 ("ray_order", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
                 ("persistent", C.c_int32), ("window_segments", C.c_int32),
-                ("bg", C.c_float * 3)]
+                ("bg", C.c_float * 3), ("no_record", C.c_int32)]
 
 
 class Grads(C.Structure):
-    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("density", C.c_void_p), ("sh", C.c_void_p), ("accumulate", C.c_int32),
+    _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("density", C.c_void_p), ("sh", C.c_void_p), ("sg", C.c_void_p),
+                ("accumulate", C.c_int32),
                 ("densify", C.c_void_p), ("densify_views", C.c_void_p)]
 
 
+class AdamGroup(C.Structure):
+    _fields_ = [("n", C.c_int64), ("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p),
+                ("v", C.c_void_p), ("lr", C.c_float)]
+
+
 EXPORTS = ("rgx_create", "rgx_destroy", "rgx_build_bvh", "rgx_bvh_destroy", "rgx_bvh_size",
-           "rgx_render_forward", "rgx_render_backward", "rgx_dump_hits", "rgx_bvh_debug",
+           "rgx_render_forward", "rgx_render_backward", "rgx_fwd_destroy", "rgx_sync_stats",
+           "rgx_false_positives", "rgx_dump_hits", "rgx_bvh_debug",
            "rgx_error_flags", "rgx_set_kernel_timing", "rgx_kernel_times", "rgx_isotropic_loss",
-           "rgx_isotropic_loss_noalloc",
+           "rgx_isotropic_loss_noalloc", "rgx_adam_step",
            "rgx_backward_replayed", "rgx_status_string", "rgx_last_error")
 
 KERNEL_KINDS = ("build", "forward", "backward", "finalize")   # RGX_KERN_* order
@@ -86,11 +96,16 @@ def load():
     L.rgx_bvh_size.argtypes = [vp]
     L.rgx_bvh_size.restype = C.c_int64
     L.rgx_render_forward.argtypes = [vp, vp, C.POINTER(Camera), C.c_int32, C.POINTER(RenderOpts),
-                                     vp, vp, vp, vp]
+                                     vp, vp, vp, C.POINTER(vp), vp]
     L.rgx_render_forward.restype = st
-    L.rgx_render_backward.argtypes = [vp, vp, C.POINTER(Camera), C.c_int32,
-                                      C.POINTER(RenderOpts), vp, vp, vp, vp, C.POINTER(Grads), vp]
+    L.rgx_render_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(Grads), vp]
     L.rgx_render_backward.restype = st
+    L.rgx_fwd_destroy.argtypes = [vp]
+    L.rgx_fwd_destroy.restype = None
+    L.rgx_sync_stats.argtypes = [vp, vp, C.POINTER(C.c_int64), vp]
+    L.rgx_sync_stats.restype = st
+    L.rgx_false_positives.argtypes = [vp, vp, C.POINTER(Camera), vp, C.c_int32, vp, vp, vp]
+    L.rgx_false_positives.restype = st
     L.rgx_dump_hits.argtypes = [vp, vp, C.POINTER(Camera), C.POINTER(RenderOpts), vp, C.c_int32,
                                 C.c_int32, vp, vp, vp, vp]
     L.rgx_dump_hits.restype = st
@@ -102,6 +117,9 @@ def load():
     L.rgx_isotropic_loss.restype = st
     L.rgx_isotropic_loss_noalloc.argtypes = [vp, C.c_int64, vp, C.c_float, vp, vp, C.c_int32, vp]
     L.rgx_isotropic_loss_noalloc.restype = st
+    L.rgx_adam_step.argtypes = [vp, C.POINTER(AdamGroup), C.c_int32, vp, C.c_float, C.c_float,
+                                C.c_float, vp]
+    L.rgx_adam_step.restype = st
     L.rgx_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.rgx_set_kernel_timing.restype = st
     L.rgx_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
@@ -154,6 +172,7 @@ def make_opts(o) -> RenderOpts:
     r.window_segments = int(getattr(o, "window_segments", 0))
     for i in range(3):
         r.bg[i] = float(o.bg[i])
+    r.no_record = int(bool(getattr(o, "no_record", False)))
     return r
 
 
@@ -207,14 +226,17 @@ class BVH:
         self.h = C.c_void_p()
 
     def build(self, means, log_scales, quats, density, sh, sh_degree, sigma_eps=0.01,
-              morton_bits=21, stream=0):
+              morton_bits=21, stream=0, sg=None):
+        n_sg = 0 if sg is None else int(sg.shape[1])
         g = Gaussians(int(means.shape[0]), int(sh_degree), means.data_ptr(),
-                      log_scales.data_ptr(), quats.data_ptr(), density.data_ptr(), sh.data_ptr())
+                      log_scales.data_ptr(), quats.data_ptr(), density.data_ptr(), sh.data_ptr(),
+                      n_sg, None if sg is None else sg.data_ptr())
         o = BuildOpts(float(sigma_eps), int(morton_bits))
         check(load().rgx_build_bvh(self.ctx.h, C.byref(g), C.byref(o), C.byref(self.h),
                                    C.c_void_p(stream)), self.ctx.h, "rgx_build_bvh")
         self.n = int(means.shape[0])
         self.sh_degree = int(sh_degree)
+        self.n_sg = n_sg
         return self
 
     def close(self):
@@ -262,26 +284,78 @@ def isotropic_loss_noalloc(ctx: Context, log_scales, r0, loss, grad, accumulate=
           ctx.h, "rgx_isotropic_loss_noalloc")
 
 
-def render_forward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, stats=None, stream=0):
+class ForwardState:
+    """Owns an rgx_fwd: what one forward rendered and what its searches
+    found, for the matching backward.  Reused in place by later forwards."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.h = C.c_void_p()
+
+    def close(self):
+        if self.h:
+            load().rgx_fwd_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def totals(self, stream=0) -> dict:
+        """Statistics totals of the forward (it must have been given stats)."""
+        out = (C.c_int64 * len(TOTAL_NAMES))()
+        check(load().rgx_sync_stats(self.ctx.h, self.h, out, C.c_void_p(stream)), self.ctx.h,
+              "rgx_sync_stats")
+        return {k: int(out[i]) for i, k in enumerate(TOTAL_NAMES)}
+
+
+def adam_step(ctx: Context, groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=0):
+    """One Adam step; groups = [(param, grad, m, v, lr)] of contiguous float32
+    device tensors, step an int32 device scalar advanced by the call."""
+    arr = (AdamGroup * len(groups))()
+    for i, (p, g, m, v, lr) in enumerate(groups):
+        arr[i] = AdamGroup(int(p.numel()), p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(),
+                           float(lr))
+    check(load().rgx_adam_step(ctx.h, arr, len(groups), step.data_ptr(), float(beta1), float(beta2),
+                               float(eps), C.c_void_p(stream)), ctx.h, "rgx_adam_step")
+
+
+def render_forward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, stats=None, stream=0,
+                   state: ForwardState | None = None):
+    """Forward render; with `state` the forward records what its backward
+    needs into it (state.h is created on first use, reused afterwards)."""
     arr = camera_array(cams)
     o = make_opts(opts)
     check(load().rgx_render_forward(ctx.h, bvh.h, arr, len(cams), C.byref(o), out_rgb.data_ptr(),
                                     out_T.data_ptr(), None if stats is None else stats.data_ptr(),
+                                    None if state is None else C.byref(state.h),
                                     C.c_void_p(stream)), ctx.h, "rgx_render_forward")
 
 
-def render_backward(ctx: Context, bvh: BVH, cams, opts, out_rgb, out_T, grad_rgb, grad_T, grads,
-                    accumulate=False, stream=0, densify=None, densify_views=None):
-    arr = camera_array(cams)
-    o = make_opts(opts)
-    g = Grads(grads["means"].data_ptr(), grads["log_scales"].data_ptr(),
-              grads["quats"].data_ptr(), grads["density"].data_ptr(), grads["sh"].data_ptr(),
-              int(bool(accumulate)), None if densify is None else densify.data_ptr(),
+def render_backward(ctx: Context, bvh: BVH, state: ForwardState, out_rgb, out_T, grad_rgb, grad_T,
+                    grads, accumulate=False, stream=0, densify=None, densify_views=None):
+    g = Grads(int(grads["means"].shape[0]), grads["means"].data_ptr(),
+              grads["log_scales"].data_ptr(), grads["quats"].data_ptr(),
+              grads["density"].data_ptr(), grads["sh"].data_ptr(),
+              grads["sg"].data_ptr() if grads.get("sg") is not None else None,
+              int(bool(accumulate)),
+              None if densify is None else densify.data_ptr(),
               None if densify_views is None else densify_views.data_ptr())
-    check(load().rgx_render_backward(ctx.h, bvh.h, arr, len(cams), C.byref(o), out_rgb.data_ptr(),
-                                     out_T.data_ptr(), grad_rgb.data_ptr(),
+    check(load().rgx_render_backward(ctx.h, bvh.h, state.h, out_rgb.data_ptr(), out_T.data_ptr(),
+                                     grad_rgb.data_ptr(),
                                      None if grad_T is None else grad_T.data_ptr(), C.byref(g),
                                      C.c_void_p(stream)), ctx.h, "rgx_render_backward")
+
+
+def false_positives(ctx: Context, bvh: BVH, cam, pix, t_end, count, stream=0):
+    """Whole-ray AABB false positives of the listed pixels' rays over
+    [t_near, t_end] (int32 counts into `count`)."""
+    c = make_camera(cam)
+    check(load().rgx_false_positives(ctx.h, bvh.h, C.byref(c), pix.data_ptr(), int(pix.numel()),
+                                     t_end.data_ptr(), count.data_ptr(), C.c_void_p(stream)),
+          ctx.h, "rgx_false_positives")
 
 
 def dump_hits(ctx: Context, bvh: BVH, cam, opts, pix, cap, seg_a, ids, count, stream=0):

@@ -37,10 +37,13 @@ def small_setup(torch_cuda):
 
 
 def _gpu_grads(torch, r, cam, o, params, gC, gT):
-    rgb, T = r.forward([cam], o)
-    g = r.backward([cam], o, rgb, T, torch.from_numpy(gC).cuda(),
+    st = r.new_state()
+    rgb, T = r.forward([cam], o, state=st)
+    g = r.backward(st, rgb, T, torch.from_numpy(gC).cuda(),
                    None if gT is None else torch.from_numpy(gT).cuda(), params)
     torch.cuda.synchronize()
+    assert r.ctx.error_flags() == 0
+    st.close()
     return {k: v.cpu().numpy() for k, v in g.items()}
 
 
@@ -65,7 +68,7 @@ def test_backward_matches_oracle(small_setup, torch_cuda, mode):
 @pytest.mark.parametrize("deg,ns", [(0, 2), (1, 16), (2, 1), (3, 4)])
 def test_backward_sh_degrees_and_segment_sizes(torch_cuda, deg, ns):
     """Every SH degree (the SH-coefficient gradients go through the per-tile
-    matrix product, masked past the degree) and segment sizes other than 8,
+    product, masked past the degree) and segment sizes other than 8,
     against the oracle adjoint."""
     sc = inputs.make_scene("cluster", 2500, 41 + deg, sh_degree=deg)
     cam = inputs.look_at_camera(29, 23, (0.2, 0.3, 2.7), fov_deg=42.0)
@@ -84,38 +87,93 @@ def test_backward_sh_degrees_and_segment_sizes(torch_cuda, deg, ns):
     r.close()
 
 
-def test_closest_hit_replay(small_setup, torch_cuda):
-    """A backward right after its forward replays the recorded closest-hit
-    results; after a forward of other rays, or after a rebuild, it searches
-    them itself.  Both give the same gradients (the same restarts)."""
+def _rel(a, b):
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_forward_state_replay(small_setup, torch_cuda):
+    """The forward state carries the forward's searches to its backward: two
+    forwards outstanding at once each replay their own record, and give the
+    gradients of a backward that searches itself (a state made with
+    no_record).  A state of another structure build is refused, and so are
+    gradient buffers of another size."""
     torch = torch_cuda
+    from paper_2509_07782_amd import lib
     sc, cam, r, params, gC, gT = small_setup
     o = _opts(adaptive=True, ess=1, t_eps=1e-4)
     other = inputs.look_at_camera(21, 17, (-0.4, 0.3, 2.5), fov_deg=40.0)
     gCt = torch.from_numpy(gC).cuda()
-    rgb, T = r.forward([cam], o)
-    g_rep = r.backward([cam], o, rgb, T, gCt, None, params)
+    rng = np.random.default_rng(3)
+    gCo = torch.from_numpy(rng.standard_normal((other.width * other.height, 3)).astype(np.float32)).cuda()
+    s1, s2, s3 = r.new_state(), r.new_state(), r.new_state()
+    rgb, T = r.forward([cam], o, state=s1)
+    rgb_o, T_o = r.forward([other], o, state=s2)         # outstanding at the same time
+    g_rep = r.backward(s1, rgb, T, gCt, None, params)
     torch.cuda.synchronize()
     assert r.ctx.backward_replayed()
-    r.forward([other], o)                      # the record now holds other rays
-    g_own = r.backward([cam], o, rgb, T, gCt, None, params)
+    g_rep_o = r.backward(s2, rgb_o, T_o, gCo, None, params)
     torch.cuda.synchronize()
-    assert not r.ctx.backward_replayed()
-    for k in PARAM_KEYS:
-        a, b = g_rep[k].cpu().numpy(), g_own[k].cpu().numpy()
-        d = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        assert d <= 1e-5, (k, d)
-    r.forward([cam], o)
-    r.build(params, sc["sh_degree"], force=True)   # a new build invalidates the record
-    r.backward([cam], o, rgb, T, gCt, None, params)
-    torch.cuda.synchronize()
-    assert not r.ctx.backward_replayed()
+    assert r.ctx.backward_replayed()
+    o_nr = _opts(adaptive=True, ess=1, t_eps=1e-4, no_record=True)
+    for cams_, rgb_, T_, g_, gref in (([cam], rgb, T, gCt, g_rep), ([other], rgb_o, T_o, gCo, g_rep_o)):
+        rgb2, T2 = r.forward(cams_, o_nr, state=s3)
+        assert torch.equal(rgb2, rgb_) and torch.equal(T2, T_)   # no_record never changes results
+        g_own = r.backward(s3, rgb2, T2, g_, None, params)
+        torch.cuda.synchronize()
+        assert not r.ctx.backward_replayed()
+        for k in PARAM_KEYS:
+            assert _rel(gref[k], g_own[k]) <= 1e-5, k
+    # a rebuild (same parameters, new build) makes the state stale
+    r.forward([cam], o, state=s1)
+    r.build(params, sc["sh_degree"], force=True)
+    with pytest.raises(lib.RgxError, match="invalid state"):
+        r.backward(s1, rgb, T, gCt, None, params)
+    # gradient buffers must match the structure's size
+    r.forward([cam], o, state=s1)
+    small = {k: v[:-1].contiguous() for k, v in params.items()}
+    with pytest.raises(lib.RgxError, match="invalid argument"):
+        r.backward(s1, rgb, T, gCt, None, small)
     # no empty-space skipping: nothing recorded, nothing replayed
     o2 = _opts(dt=0.005, ess=0)
-    rgb2, T2 = r.forward([cam], o2)
-    r.backward([cam], o2, rgb2, T2, gCt, None, params)
+    rgb2, T2 = r.forward([cam], o2, state=s1)
+    r.backward(s1, rgb2, T2, gCt, None, params)
     torch.cuda.synchronize()
     assert not r.ctx.backward_replayed()
+    assert r.ctx.error_flags() == 0
+    for st in (s1, s2, s3):
+        st.close()
+
+
+def test_autograd_stale_structure_rebuilds(small_setup, torch_cuda):
+    """render(A); render(B); backward of A: the structure now holds B, so
+    A's backward rebuilds A and renders it again; its gradients equal those
+    of A's backward taken right away."""
+    torch = torch_cuda
+    from paper_2509_07782_amd.render import Renderer, render
+    sc, cam, _, _, _, _ = small_setup
+    o = _opts(adaptive=True, ess=1, t_eps=1e-4)
+    rr = Renderer(0)
+    pa = {k: v.clone().requires_grad_(True) for k, v in to_device(sc).items()}
+    sub = {k: v[: len(v) * 2 // 3] for k, v in sc.items() if k in PARAM_KEYS}
+    sub["sh_degree"] = sc["sh_degree"]
+    pb = {k: v.clone().requires_grad_(True) for k, v in to_device(sub).items()}
+    rgb_a, _ = render(pa, sc["sh_degree"], rr, [cam], o)
+    (rgb_a ** 2).sum().backward()
+    ref = {k: pa[k].grad.clone() for k in PARAM_KEYS}
+    for k in PARAM_KEYS:
+        pa[k].grad = None
+    rgb_a, _ = render(pa, sc["sh_degree"], rr, [cam], o)
+    rgb_b, _ = render(pb, sc["sh_degree"], rr, [cam], o)     # fewer Gaussians
+    (rgb_a ** 2).sum().backward()
+    (rgb_b ** 2).sum().backward()
+    torch.cuda.synchronize()
+    for k in PARAM_KEYS:
+        assert pa[k].grad.shape == pa[k].shape
+        assert _rel(pa[k].grad, ref[k]) <= 1e-5, k
+        assert pb[k].grad.shape == pb[k].shape
+    rr.check_errors()
+    rr.close()
 
 
 def test_window_replay_dense_chunked(torch_cuda):
@@ -129,19 +187,26 @@ def test_window_replay_dense_chunked(torch_cuda):
     cam = inputs.look_at_camera(40, 32, (0.2, 0.1, 2.4), fov_deg=35.0)
     r, params = renderer_for(sc)
     o = _opts(adaptive=True, ess=1, t_eps=1e-4, window_segments=4)
-    rgb, T, st = r.forward([cam], o, stats=True)
+    s1, s2 = r.new_state(), r.new_state()
+    rgb, T, st = r.forward([cam], o, stats=True, state=s1)
     torch.cuda.synchronize()
     from paper_2509_07782_amd import lib
     chunked = int(st[:, lib.STAT_NAMES.index("chunked")].sum())
     assert chunked > 0
+    tot = s1.totals()
+    assert tot["chunked"] == chunked and tot["rays"] == cam.width * cam.height
+    assert tot["Q"] == int(st[:, 0].sum())
+    # every tile's searches fit the record (the pool has a floor for calls of
+    # few tiles), so the backward replays the recorded chunks
+    assert tot["unrecorded"] == 0
     rng = np.random.default_rng(13)
     gCt = torch.from_numpy(rng.standard_normal((cam.width * cam.height, 3)).astype(np.float32)).cuda()
-    g_rep = r.backward([cam], o, rgb, T, gCt, None, params)
+    g_rep = r.backward(s1, rgb, T, gCt, None, params)
     torch.cuda.synchronize()
     assert r.ctx.backward_replayed()
-    other = inputs.look_at_camera(16, 16, (-0.3, 0.2, 2.6), fov_deg=35.0)
-    r.forward([other], o)
-    g_own = r.backward([cam], o, rgb, T, gCt, None, params)
+    r.forward([cam], _opts(adaptive=True, ess=1, t_eps=1e-4, window_segments=4, no_record=True),
+              state=s2)
+    g_own = r.backward(s2, rgb, T, gCt, None, params)
     torch.cuda.synchronize()
     assert not r.ctx.backward_replayed()
     for k in PARAM_KEYS:

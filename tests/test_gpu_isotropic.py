@@ -63,8 +63,8 @@ def test_isotropic_loss_matches_oracle(torch_cuda):
 def test_isotropic_descent_lowers_false_positives(torch_cuda):
     """Outdoor stress scene (3M Gaussians, log-scale spread 1.0): descending
     the isotropic loss on the log-scales drives the ratio bound below r0 and
-    lowers the per-ray count of leaves whose AABB meets a ray's window while
-    the ellipsoid does not."""
+    lowers the per-ray count of Gaussians whose AABB meets the ray while the
+    ellipsoid does not (whole-ray AABB false positives)."""
     torch = torch_cuda
     sc = inputs.config_scene(4, regularized=False, log_scale_sd=1.0)
     cams = inputs.config_cameras(4)
@@ -72,9 +72,15 @@ def test_isotropic_descent_lowers_false_positives(torch_cuda):
     o = RenderOptions(adaptive=True, ess=1, t_eps=1e-4, persistent=True)
 
     def box_only(scene):
+        """Whole-ray AABB false positives per ray on every 16th pixel of
+        every 16th row of the first view."""
+        from paper_2509_07782_amd import lib
         rend, _ = renderer_for(scene)
-        _, _, st = rend.forward(cams, o, stats=True)
-        v = float(st[:, 5].double().mean())
+        _, _, st = rend.forward(cams[:1], o, stats=True)
+        t_end = st[:, lib.STAT_T_END].contiguous().view(torch.float32)
+        pix = torch.from_numpy(inputs.pixel_subset(cams[0], 16).astype(np.int32)).cuda()
+        v = float(rend.false_positives(cams[0], pix, t_end[pix.long()].contiguous()).double().mean())
+        rend.check_errors()
         rend.close()
         return v
 
@@ -93,6 +99,6 @@ def test_isotropic_descent_lowers_false_positives(torch_cuda):
     frac1 = float((_ratio(sc2["log_scales"]) > r0).mean())
     after = box_only(sc2)
     r.close()
-    print(f"ratio>r0: {frac0:.3f} -> {frac1:.3f}; AABB-only leaves per ray {before:.1f} -> {after:.1f}")
+    print(f"ratio>r0: {frac0:.3f} -> {frac1:.3f}; AABB false positives per ray {before:.1f} -> {after:.1f}")
     assert frac0 > 0.2 and frac1 < 0.25 * frac0
     assert after < before

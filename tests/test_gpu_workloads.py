@@ -35,21 +35,25 @@ def _view_offsets(cams):
     return out
 
 
-def _check_pixels(rgb, orgb, mg, frac_bad=0.002):
+def _check_pixels(rgb, orgb, mg, frac_bad=0.001):
+    """Every pixel within 1e-4 of the oracle, except rays whose oracle
+    decisions had a near tie (margin below 1e-6: an inclusion, termination
+    or emptiness decision); those stay below 0.1 % of the rays."""
     err = np.abs(rgb - orgb).max(axis=1)
     bad = err > 1e-4
     assert bad.mean() <= frac_bad, (bad.sum(), err.max())
-    assert np.all(mg[bad] < 1e-5), mg[bad]
+    assert np.all(mg[bad] < 1e-6), mg[bad]
     return err
 
 
 def test_config2_full_size(torch_cuda):
     """100k Gaussians, 800x800: fixed-step and adaptive pixels against the
-    oracle on a stride-16 subset; Morton tiles == scanline bit for bit."""
+    oracle on every second pixel of every second row; Morton tiles ==
+    scanline bit for bit."""
     sc = inputs.config_scene(2)
     cam = inputs.config_cameras(2)[0]
     r, _ = renderer_for(sc)
-    pix = inputs.pixel_subset(cam, 16)
+    pix = inputs.pixel_subset(cam, 2)
     for o in (_opts(dt=0.005, ess=1, t_eps=1e-4), _opts(adaptive=True, ess=1, t_eps=1e-4)):
         rgb, T = (x.cpu().numpy() for x in r.forward([cam], o))
         orgb, oT, ost, mg = oracle.render(sc, cam, oracle_opts(o), pix)
@@ -57,6 +61,7 @@ def test_config2_full_size(torch_cuda):
         _check_pixels(rgb[pix], orgb, mg)
         raster = [x.cpu().numpy() for x in r.forward([cam], _opts(**{**o.__dict__, "ray_order": 0}))]
         assert np.array_equal(raster[0], rgb) and np.array_equal(raster[1], T)
+    assert r.ctx.error_flags() == 0
 
 
 @pytest.fixture(scope="module")
@@ -67,25 +72,50 @@ def config3(torch_cuda):
     return sc, cams, r, params
 
 
-def test_config3_sampled_pixels(config3):
-    """1M Gaussians, 4 views 1024x768, the benchmark's sampling (adaptive,
-    closest-hit restarts, T_eps 1e-4): every 64th pixel against the oracle."""
+def test_config3_benchmark_mode_pixels_and_gradients(config3, torch_cuda):
+    """1M Gaussians, 4 views 1024x768, in the benchmark's mode (adaptive
+    steps, closest-hit restarts, T_eps 1e-4, persistent launch, the forward's
+    searches recorded and replayed by the backward): every 16th pixel of
+    every 16th row of every view against the oracle, and the gradients of a
+    loss on those pixels against the oracle adjoint of the same loss."""
+    torch = torch_cuda
     sc, cams, r, params = config3
     o = _opts(adaptive=True, ess=1, t_eps=1e-4, persistent=True)
-    rgb, T = (x.cpu().numpy() for x in r.forward(cams, o))
+    st = r.new_state()
+    rgb, T = r.forward(cams, o, state=st)
+    rgb_np = rgb.cpu().numpy()
+    R = rgb.shape[0]
+    rng = np.random.default_rng(3)
+    gC = np.zeros((R, 3), np.float32)
+    ref = None
+    oo = oracle_opts(o)
     for c, off in zip(cams, _view_offsets(cams)):
-        pix = inputs.pixel_subset(c, 64)
-        orgb, oT, ost, mg = oracle.render(sc, c, oracle_opts(o), pix)
-        _check_pixels(rgb[off + pix], orgb, mg)
+        pix = inputs.pixel_subset(c, 16)
+        orgb, oT, ost, mg = oracle.render(sc, c, oo, pix)
+        _check_pixels(rgb_np[off + pix], orgb, mg)
+        w = rng.standard_normal((len(pix), 3)).astype(np.float32)
+        gC[off + pix] = w
+        g = oracle.backward(sc, c, oo, pix, w.astype(np.float64), None)
+        ref = g if ref is None else {k: ref[k] + g[k] for k in PARAM_KEYS}
+    gg = r.backward(st, rgb, T, torch.from_numpy(gC).cuda(), None, params)
+    torch.cuda.synchronize()
+    assert r.ctx.backward_replayed()
+    assert r.ctx.error_flags() == 0
+    st.close()
+    got = {k: v.cpu().numpy() for k, v in gg.items()}
+    for k, (rel, frac) in grad_rel_errors(got, ref).items():
+        assert rel <= 1e-3, (k, rel)
+        assert frac >= 0.999, (k, frac)
 
 
-def test_config3_masked_gradients(config3, torch_cuda):
-    """Gradients of a loss on every 64th pixel of the 4 views, full 1M scene,
-    against the oracle adjoint of the same loss."""
+def test_config3_fixed_step_masked_gradients(config3, torch_cuda):
+    """Fixed step, T_eps 0 (no near ties at all): gradients of a loss on
+    every 64th pixel of the 4 views against the oracle adjoint."""
     torch = torch_cuda
     sc, cams, r, params = config3
     o = _opts(dt=0.005, ess=1, t_eps=0.0, persistent=True)
-    rgb, T = r.forward(cams, o)
+    st = r.new_state()
+    rgb, T = r.forward(cams, o, state=st)
     R = rgb.shape[0]
     rng = np.random.default_rng(3)
     gC = np.zeros((R, 3), np.float32)
@@ -97,8 +127,10 @@ def test_config3_masked_gradients(config3, torch_cuda):
         gC[off + pix] = w
         g = oracle.backward(sc, c, oracle_opts(o), pix, w.astype(np.float64), None)
         ref = g if ref is None else {k: ref[k] + g[k] for k in PARAM_KEYS}
-    gg = r.backward(cams, o, rgb, T, torch.from_numpy(gC).cuda(), None, params)
+    gg = r.backward(st, rgb, T, torch.from_numpy(gC).cuda(), None, params)
     torch.cuda.synchronize()
+    assert r.ctx.error_flags() == 0
+    st.close()
     got = {k: v.cpu().numpy() for k, v in gg.items()}
     for k, (rel, frac) in grad_rel_errors(got, ref).items():
         assert rel <= 1e-3, (k, rel)
@@ -118,7 +150,8 @@ def test_fd_4096_gaussian_subset(torch_cuda):
     r = Renderer(0, sigma_eps=1e-30)
     params = to_device(sc)
     r.build(params, 3)
-    rgb, T = r.forward(cams, o)
+    st = r.new_state()
+    rgb, T = r.forward(cams, o, state=st)
     R = rgb.shape[0]
     rng = np.random.default_rng(11)
     gC = np.zeros((R, 3), np.float32)
@@ -128,8 +161,9 @@ def test_fd_4096_gaussian_subset(torch_cuda):
         w = rng.standard_normal((len(pix), 3)).astype(np.float32)
         gC[off + pix] = w
         subs.append((c, pix, w.astype(np.float64)))
-    gg = r.backward(cams, o, rgb, T, torch.from_numpy(gC).cuda(), None, params)
+    gg = r.backward(st, rgb, T, torch.from_numpy(gC).cuda(), None, params)
     torch.cuda.synchronize()
+    assert r.ctx.error_flags() == 0
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in gg.items()}
     ref = None
     for c, pix, w in subs:
@@ -157,30 +191,59 @@ def test_fd_4096_gaussian_subset(torch_cuda):
             base[k][idx] -= 2 * h
             lm = loss(base)
             fd = (lp - lm) / (2 * h)
-            scale = np.abs(ref[k]).max()
-            assert abs(got[k][idx] - fd) <= 2e-3 * scale + 1e-3 * abs(fd), (k, idx, got[k][idx], fd)
+            # the oracle adjoint against FP64 differences, element by element
+            assert abs(ref[k][idx] - fd) <= 1e-3 * abs(fd) + 1e-6 * np.abs(ref[k]).max(), \
+                (k, idx, ref[k][idx], fd)
+            # the GPU against FP64 differences: 1e-3 relative on entries that
+            # are not tiny next to the tensor's largest
+            if abs(fd) >= 1e-2 * np.abs(ref[k]).max():
+                assert abs(got[k][idx] - fd) <= 1e-3 * abs(fd), (k, idx, got[k][idx], fd)
+            else:
+                assert abs(got[k][idx] - fd) <= 1e-5 * np.abs(ref[k]).max(), (k, idx, got[k][idx], fd)
 
 
 def test_config4_false_positives_and_parity(torch_cuda):
     """Outdoor layout (3M Gaussians, shell to r = 50, 1297x840 views from
-    inside): the scale-regularised scene has fewer AABB-only leaf tests per
-    ray than the unregularised one (stress log-scale spread 1.0); sampled
-    pixels against the oracle."""
+    inside), stress log-scale spread 1.0.  Whole-ray AABB false positives
+    (Sec. 3.4, Eq. 6) on every 16th pixel of every 16th row: the GPU count
+    equals the oracle's up to each ray's near ties, and the scale-regularised
+    scene has fewer per ray than the unregularised one.  Pixels of the
+    regularised scene on the same subset of every view against the oracle."""
+    torch = torch_cuda
+    from paper_2509_07782_amd import lib
     cams = inputs.config_cameras(4)
-    counts = {}
+    fp = {}
+    o = _opts(adaptive=True, ess=1, t_eps=1e-4, persistent=True)
+    oo = oracle_opts(o)
     for reg in (False, True):
         sc = inputs.config_scene(4, regularized=reg, log_scale_sd=1.0)
         r, _ = renderer_for(sc)
-        o = _opts(adaptive=True, ess=1, t_eps=1e-4, persistent=True)
-        rgb, T, st = (x.cpu().numpy() for x in r.forward(cams, o, stats=True))
-        counts[reg] = st[:, 5].mean()
-        if reg:
-            c, off = cams[1], _view_offsets(cams)[1]
-            pix = inputs.pixel_subset(c, 128)
-            orgb, oT, ost, mg = oracle.render(sc, c, oracle_opts(o), pix)
-            _check_pixels(rgb[off + pix], orgb, mg)
+        rgb, T, st = r.forward(cams, o, stats=True)
+        t_end = st[:, lib.STAT_T_END].contiguous().view(torch.float32)
+        rgb = rgb.cpu().numpy()
+        counts = []
+        for vi, (c, off) in enumerate(zip(cams, _view_offsets(cams))):
+            pix = inputs.pixel_subset(c, 16)
+            pix_t = torch.from_numpy(pix.astype(np.int32)).cuda()
+            te = t_end[off + pix_t.long()].contiguous()
+            cnt = r.false_positives(c, pix_t, te).cpu().numpy().astype(np.int64)
+            counts.append(cnt)
+            if vi == 0:
+                ocnt, oties, ot_end = oracle.false_positives(sc, c, oo, pix)
+                same_end = np.abs(te.cpu().numpy() - ot_end) <= 1e-5 * np.maximum(1.0, ot_end)
+                assert same_end.mean() >= 0.99
+                d = np.abs(cnt - ocnt)[same_end]
+                assert np.all(d <= oties[same_end]), d.max()
+                assert (d == 0).mean() >= 0.98
+            if reg:
+                orgb, oT, ost, mg = oracle.render(sc, c, oo, pix)
+                _check_pixels(rgb[off + pix], orgb, mg)
+        fp[reg] = float(np.concatenate(counts).mean())
+        assert r.ctx.error_flags() == 0
         r.close()
-    assert counts[True] < counts[False], counts
+    print(f"whole-ray AABB false positives per ray: unregularised {fp[False]:.1f}, "
+          f"regularised {fp[True]:.1f}")
+    assert fp[True] < fp[False], fp
 
 
 def test_config5_batched_persistent_and_graph(torch_cuda):
@@ -201,6 +264,19 @@ def test_config5_batched_persistent_and_graph(torch_cuda):
         n = c.width * c.height
         assert torch.equal(one[0], rgb[off:off + n]) and torch.equal(one[1], T[off:off + n])
         off += n
+    # every 32nd pixel of every 32nd row of the 16 views against the oracle
+    rgb_np = rgb.cpu().numpy()
+    oo = oracle_opts(ob)
+    got, want, margins = [], [], []
+    for c, off in zip(cams, _view_offsets(cams)):
+        pix = inputs.pixel_subset(c, 32)
+        orgb, oT, ost, mg = oracle.render(sc, c, oo, pix)
+        got.append(rgb_np[off + pix])
+        want.append(orgb)
+        margins.append(mg)
+    _check_pixels(np.concatenate(got), np.concatenate(want), np.concatenate(margins))
+    assert sum(len(m) for m in margins) > 10000
+    assert r.ctx.error_flags() == 0
     # captured fwd + loss + bwd, replayed
     R = rgb.shape[0]
     target = torch.from_numpy(inputs.target_image(5, R)).cuda()
@@ -225,6 +301,7 @@ def test_config5_batched_persistent_and_graph(torch_cuda):
     for k in PARAM_KEYS:
         d = (step.grads[k] - g0[k]).norm() / max(float(g0[k].norm()), 1e-30)
         assert d <= 1e-5, (k, float(d))
+    r.check_errors()
 
 
 def test_autotuner_keeps_images(torch_cuda):
@@ -238,6 +315,7 @@ def test_autotuner_keeps_images(torch_cuda):
     a = r.forward(cams, o)
     b = r.forward(cams, best)
     assert all(bool((x == y).all()) for x, y in zip(a, b))
+    r.check_errors()
 
 
 @pytest.mark.parametrize("case", ["single", "pair", "inactive", "inside", "near_far", "bg"])
@@ -264,6 +342,7 @@ def test_edge_cases(torch_cuda, case):
         o = _opts(dt=0.005, ess=2, t_eps=1e-4, bg=(0.3, 0.6, 0.9))
     r, _ = renderer_for(sc)
     rgb, T = (x.cpu().numpy() for x in r.forward([cam], o))
+    r.check_errors()
     orgb, oT, _, _ = oracle.render(sc, cam, oracle_opts(o))
     assert np.abs(rgb - orgb).max() <= 1e-4
     assert np.abs(T - oT).max() <= 1e-4
