@@ -433,22 +433,24 @@ __device__ __forceinline__ float wave_sum_slots16(const float *g, int lane) {
   return u;
 }
 
-// SH-coefficient gradients of a batch of up to 16 Gaussians.  For Gaussian
-// b of the batch and channel c, dL/df_{m,c} = sum over the tile's rays r of
-// S_b(r) Y_m(d_r) G_c(r), S_b(r) the ray's sum over samples of w_k T_k phi_k
-// (zero where the ray misses b).  A_c[r][m] = Y_m(d_r) G_c(r) is fixed for
-// the tile and held in registers: lane L keeps column m = L & 15 for the
-// rays r = 4q + (L >> 4), q = 0..15.  S[b][r] is staged in LDS for the
-// batch.  Per Gaussian, each lane sums its 16 rays for its column (three
-// channels, 48 FMAs), two cross-lane adds finish the sum over the four ray
-// groups, and lanes 0-15 add 16 consecutive floats per channel to the
-// Gaussian's row.  (The batch is a small dense product; it runs on the
-// vector units: a matrix-core version measured 3.9 % faster on the
-// backward, not worth a second kind of arithmetic unit on this path.)
-constexpr int kSbStride = 66;   // floats per staged row
+// SH-coefficient gradients of a batch of up to 16 Gaussians, a small dense
+// product on the matrix cores.  For Gaussian b of the batch and channel c,
+// dL/df_{m,c} = sum over the tile's rays r of Y_m(d_r) G_c(r) S_b(r), S_b(r)
+// the ray's sum over samples of w_k T_k phi_k (zero where the ray misses b).
+// With A_c[m][r] = Y_m(d_r) G_c(r) fixed for the tile (held in registers)
+// and B[r][b] = S_b(r) staged in LDS, each channel is 16 chained 16x16x4 FP32
+// MFMAs over the 64 rays.  Operand layout of v_mfma_f32_16x16x4_f32 (wave64):
+// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
+// j + 16 (i / 4), register i % 4.  Each atomic instruction therefore adds
+// 4 floats to each of 16 Gaussians' rows: spread over 16 cache lines, the
+// atomics resolve in parallel in L2 (the transposed product, 16 consecutive
+// floats of 4 Gaussians per instruction, made the backward 3.5 % slower in
+// spite of a third of the atomic write traffic).
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kSbStride = 66;   // floats per staged row: transposed reads hit distinct banks
 
 struct ShBatch {
-  float a[3][16];   // A_c for rays 4q + (lane >> 4), column m = lane & 15
+  float a[3][16];   // A_c for rays 4q + (lane >> 4), row m = lane & 15
   int n = 0;        // uniform: staged Gaussians
   int id = 0;       // lane b < 16: the Gaussian staged in row b
 };
@@ -479,28 +481,25 @@ __device__ __forceinline__ void sh_batch_flush(ShBatch &B, const float *sb, floa
                                                int lane) {
   if (B.n == 0) return;
   __builtin_amdgcn_wave_barrier();
-  const int m = lane & 15, k = lane >> 4;
-  for (int b = 0; b < B.n; b++) {
-    float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f;
+  f4v d0 = {0.0f, 0.0f, 0.0f, 0.0f}, d1 = d0, d2 = d0;
 #pragma unroll
-    for (int q = 0; q < 16; q++) {
-      const float sv = sb[b * kSbStride + 4 * q + k];
-      d0 = fmaf(sv, B.a[0][q], d0);
-      d1 = fmaf(sv, B.a[1][q], d1);
-      d2 = fmaf(sv, B.a[2][q], d2);
-    }
-    d0 += __shfl_xor(d0, 32, 64);
-    d0 += __shfl_xor(d0, 16, 64);
-    d1 += __shfl_xor(d1, 32, 64);
-    d1 += __shfl_xor(d1, 16, 64);
-    d2 += __shfl_xor(d2, 32, 64);
-    d2 += __shfl_xor(d2, 16, 64);
-    const int jb = __shfl(B.id, b, 64);
-    if (k == 0 && m < sh_k) {
-      float *row = acc + (size_t)kAccFloats * jb + 16;
-      unsafeAtomicAdd(row + m, d0);
-      unsafeAtomicAdd(row + 16 + m, d1);
-      unsafeAtomicAdd(row + 32 + m, d2);
+  for (int q = 0; q < 16; q++) {
+    const float bv = sb[(lane & 15) * kSbStride + 4 * q + (lane >> 4)];
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[0][q], bv, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[1][q], bv, d1, 0, 0, 0);
+    d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[2][q], bv, d2, 0, 0, 0);
+  }
+  const int jb = __shfl(B.id, lane & 15, 64);
+  if ((lane & 15) < B.n) {
+    float *row = acc + (size_t)kAccFloats * jb + 16;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int m = 4 * (lane >> 4) + i;
+      if (m < sh_k) {
+        unsafeAtomicAdd(row + m, d0[i]);
+        unsafeAtomicAdd(row + 16 + m, d1[i]);
+        unsafeAtomicAdd(row + 32 + m, d2[i]);
+      }
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -1890,8 +1889,8 @@ __device__ __forceinline__ void sg_slots(const float *sg, float *sgacc, int j, f
 // geometry and density slots are summed over the wave (DPP and half-wave
 // swaps) before one atomic per slot; the SH-coefficient slots, a per-ray
 // constant times one scalar per (ray, Gaussian), are staged 16 Gaussians at a
-// time and multiplied out per batch.  Two waves per SIMD: the tile's operand
-// and the staging buffer need the registers and LDS.
+// time and multiplied out on the matrix cores.  Two waves per SIMD: the
+// tile's matrix operand and the staging buffer need the registers and LDS.
 
 template <int NS, bool SG = false>
 __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt, MarchOpts op,
@@ -2109,7 +2108,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
             v[15] = ds * inv_sig;
           }
           // slots [0,16): geometry and density, summed over the wave; the SH
-          // slots go through the per-tile batch
+          // slots go through the matrix-core batch
           sb[shb.n * kSbStride + lane] = S;
           shb.id = lane == shb.n ? j : shb.id;
           const float mine = wave_sum_slots16(v, lane);

@@ -68,7 +68,7 @@ def test_backward_matches_oracle(small_setup, torch_cuda, mode):
 @pytest.mark.parametrize("deg,ns", [(0, 2), (1, 16), (2, 1), (3, 4)])
 def test_backward_sh_degrees_and_segment_sizes(torch_cuda, deg, ns):
     """Every SH degree (the SH-coefficient gradients go through the per-tile
-    product, masked past the degree) and segment sizes other than 8,
+    matrix product, masked past the degree) and segment sizes other than 8,
     against the oracle adjoint."""
     sc = inputs.make_scene("cluster", 2500, 41 + deg, sh_degree=deg)
     cam = inputs.look_at_camera(29, 23, (0.2, 0.3, 2.7), fov_deg=42.0)
