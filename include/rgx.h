@@ -34,7 +34,9 @@
  *    anything is enqueued.  Data-dependent cases are not errors: a Gaussian
  *    with sigma~ <= sigma_eps, a zero quaternion or a non-finite parameter is
  *    inactive (never hit, zero gradient).  HIP failures return RGX_ERR_HIP with
- *    the HIP message in rgx_last_error().
+ *    the HIP message in rgx_last_error(); an error left pending by the
+ *    caller's own earlier HIP calls is cleared on entry to a call that
+ *    launches work, so it is never reported as the library's.
  */
 #ifndef RGX_H
 #define RGX_H
@@ -222,7 +224,8 @@ int64_t rgx_bvh_size(const rgx_bvh *bvh);
    tile on average; a tile that does not fit is not recorded and its backward
    searches again, with the same results).  With `stats` given, the state
    also receives the totals that rgx_sync_stats returns.  Any number of states
-   may be outstanding; each belongs to one forward at a time. */
+   may be outstanding; each belongs to one forward at a time.  If the call
+   fails after a new handle was made, *state still holds it: destroy it. */
 rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera *cams,
                               int32_t n_views, const rgx_render_opts *opts, float *out_rgb,
                               float *out_T, int32_t *stats, rgx_fwd **state, hipStream_t stream);

@@ -38,6 +38,7 @@ def gpu_render(r, cams, opts, stats=False):
     import torch
     out = r.forward(cams, opts, stats=stats)
     torch.cuda.synchronize()
+    assert r.ctx.error_flags() == 0
     return tuple(x.cpu().numpy() for x in out)
 
 
