@@ -220,9 +220,11 @@ int64_t rgx_bvh_size(const rgx_bvh *bvh);
    handle can be captured into a graph once a first call has sized them).
    With empty-space skipping on (and the BVH in use) the state records each
    ray's first four closest-hit results (Alg. 1 ClosestHit, Eq. 4; 16 B per
-   ray) and every window list its tiles collected (a pool of 48 KB per 64-ray
-   tile on average; a tile that does not fit is not recorded and its backward
-   searches again, with the same results).  With `stats` given, the state
+   ray), every window list its tiles collected, and each segment's
+   per-sample sums of density and colour (Eq. 3; 128 B per ray segment at
+   N_s = 8), in a pool of 96 KB per 64-ray tile on average; a tile that does
+   not fit is not recorded and its backward searches and sums again, with
+   the same results.  With `stats` given, the state
    also receives the totals that rgx_sync_stats returns.  Any number of states
    may be outstanding; each belongs to one forward at a time.  If the call
    fails after a new handle was made, *state still holds it: destroy it. */
@@ -236,9 +238,10 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
    dL/d(parameters) in user order.  The cameras and options are the state's.
    The sample schedule, the ESS restarts and the truncation boundaries are
    treated as constants.  Segments are taken in the forward's deterministic
-   order, the recorded closest hits and window lists replayed; the
-   transmittance before every sample is recomputed, and the colour still to
-   come behind a sample is the final colour minus the running prefix.
+   order, the recorded closest hits, window lists and per-sample sums
+   replayed; the transmittance before every sample is recomputed from those
+   sums, and the colour still to come behind a sample is the final colour
+   minus the running prefix.
    RGX_ERR_STATE when `bvh` is not the structure build the forward rendered
    (rebuilt or replaced since) or the state belongs to another context;
    RGX_ERR_INVALID_ARG when grads->n differs from the structure's n. */

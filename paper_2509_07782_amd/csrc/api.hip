@@ -566,9 +566,10 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
     f->recorded = false;
     f->has_totals = false;
     // record the searches for the backward: each ray's first closest-hit
-    // results and every window list of every tile
+    // results, every window list of every tile and each segment step's
+    // per-sample sums
     const size_t need = (size_t)rays * kReplayK * sizeof(float);
-    // a shared pool: 48 KB per tile on average, at least 64 MB so that a
+    // a shared pool: 96 KB per tile on average, at least 64 MB so that a
     // call of few tiles with long window lists still records them all
     const size_t pool = std::min<size_t>(
         std::max<size_t>(2 + (size_t)tiles * kWrecDwordsPerTile, (size_t)1 << 24), 0xfffffff0u);

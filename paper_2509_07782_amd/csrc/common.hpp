@@ -85,7 +85,14 @@ constexpr int kReplayK = 4;
 // incomplete and is not replayed.
 constexpr int kWrecHeader = 7;
 constexpr uint32_t kWrecNone = 0xffffffffu;
-constexpr int kWrecDwordsPerTile = 12288;   // pool size per tile of the call (average)
+// Sample record: after every segment step of a tile the forward appends
+// [next, hit-lane mask (2 dwords), empty-lane mask (2 dwords)], then for the
+// lanes whose segment hit some Gaussian the per-sample sums sigma_k and the
+// colour sum W_k (4 N_S floats per lane, stored as [k][component][lane rank]),
+// then for the lanes whose segment was empty the restart distance it found.
+constexpr int kSrecHeader = 5;
+// pool size per tile of the call (average): window lists and sample records
+constexpr int kWrecDwordsPerTile = 24576;
 
 // Scalar (constant address space) views of read-only scene data: a
 // wave-uniform address loads once into SGPRs for the whole wave.

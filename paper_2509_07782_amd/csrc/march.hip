@@ -1417,6 +1417,81 @@ __device__ __forceinline__ void rec_put_marks(WinRec &R, const MarchOpts &op, co
   }
 }
 
+// The per-sample sums of a segment step (layout next to kSrecHeader): lanes
+// `hit` store sigma_k and W_k, lanes `empty` their restart distance.
+template <int NS>
+__device__ __forceinline__ void rec_put_samples(WinRec &R, const MarchOpts &op, bool hit,
+                                                bool empty, float best, const float *sg,
+                                                const float *W0, const float *W1,
+                                                const float *W2, int lane) {
+  if (!R.ok) return;
+  const uint64_t hm = ballot(hit), em = ballot(empty);
+  const int nh = __popcll(hm), ne = __popcll(em);
+  const uint32_t off = rec_alloc(R, op, kSrecHeader + 4 * NS * nh + ne, lane);
+  if (off == kWrecNone) return;
+  uint32_t *p = op.wrec + off;
+  if (lane == 0) {
+    p[1] = (uint32_t)hm; p[2] = (uint32_t)(hm >> 32);
+    p[3] = (uint32_t)em; p[4] = (uint32_t)(em >> 32);
+  }
+  float *q = reinterpret_cast<float *>(p + kSrecHeader);
+  const uint64_t below = lanes_below(lane);
+  if (hit) {
+    const int rk = __popcll(hm & below);
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+      q[(4 * k) * nh + rk] = sg[k];
+      q[(4 * k + 1) * nh + rk] = W0[k];
+      q[(4 * k + 2) * nh + rk] = W1[k];
+      q[(4 * k + 3) * nh + rk] = W2[k];
+    }
+  }
+  if (empty) q[4 * NS * nh + __popcll(em & below)] = best;
+}
+
+// Reads the sample record of a segment step back: sigma_k into sg, G . W_k
+// into GW, and for an empty segment the restart distance into *best.
+// Returns whether this lane's segment hit something.  A record that does not
+// match the lanes that march (cannot happen) is reported, and its lanes read
+// as empty with no restart.
+template <int NS>
+__device__ __forceinline__ bool rec_get_samples(WinRec &R, const MarchOpts &op, bool go, float Gc0,
+                                                float Gc1, float Gc2, float *sg, float *GW,
+                                                float *best, int lane, int32_t *err) {
+  *best = kInf;
+  const uint32_t off = R.cur;
+  if (off == kWrecNone || !rec_fits(op, off, kSrecHeader)) {
+    if (err) *err = 5;
+    R.cur = kWrecNone;
+    return false;
+  }
+  const uint32_t *p = op.wrec + off;
+  const uint64_t hm = ((uint64_t)(uint32_t)uniform_int((int)p[2]) << 32) | (uint32_t)uniform_int((int)p[1]);
+  const uint64_t em = ((uint64_t)(uint32_t)uniform_int((int)p[4]) << 32) | (uint32_t)uniform_int((int)p[3]);
+  const int nh = __popcll(hm), ne = __popcll(em);
+  if ((hm | em) != ballot(go) || (hm & em) != 0 ||
+      !rec_fits(op, off, kSrecHeader + 4 * (uint64_t)NS * nh + ne)) {
+    if (err) *err = 5;
+    R.cur = kWrecNone;
+    return false;
+  }
+  R.cur = (uint32_t)uniform_int((int)p[0]);
+  const float *q = reinterpret_cast<const float *>(p + kSrecHeader);
+  const uint64_t below = lanes_below(lane);
+  const bool hit = (hm >> lane) & 1ull;
+  if (hit) {
+    const int rk = __popcll(hm & below);
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+      sg[k] = q[(4 * k) * nh + rk];
+      GW[k] = fmaf(Gc0, q[(4 * k + 1) * nh + rk],
+                   fmaf(Gc1, q[(4 * k + 2) * nh + rk], Gc2 * q[(4 * k + 3) * nh + rk]));
+    }
+  }
+  if ((em >> lane) & 1ull) *best = q[4 * NS * nh + __popcll(em & below)];
+  return hit;
+}
+
 // Loads the chunk at pool offset `off` into the list (identity order, no
 // marks); returns its collection's result and the next record in *next.
 __device__ __forceinline__ int rec_load(const MarchOpts &op, WaveMem &M, uint32_t off, int lane,
@@ -1798,6 +1873,9 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
         });
       }
+      // the step's per-sample sums and restarts, for a replaying backward
+      if (op.replay_mode == 1)
+        rec_put_samples<NS>(rec, op, go && nhit > 0, empty, best, sg, W0, W1, W2, lane);
       if (go) {
         if (nhit > 0) {
           if (stats) { cnt[ST_SEGMENTS]++; cnt[ST_P] += nhit; }
@@ -1883,9 +1961,11 @@ __device__ __forceinline__ void sg_slots(const float *sg, float *sgacc, int j, f
 
 // ---------------------------------------------------------------------------
 // Backward kernel: replays the forward's segments from the same window lists
-// (or brute force / depth-first sources) in the same order, recomputes the
-// transmittance before every sample, derives dL/dsigma_k and dL/dW_k, then
-// revisits the Gaussians some lane hit for their parameter adjoints.  The 16
+// (or brute force / depth-first sources) in the same order, takes each
+// segment's per-sample sums from the forward's record (or sums them again
+// where there is none), recomputes the transmittance before every sample,
+// derives dL/dsigma_k and dL/dW_k, then revisits the Gaussians some lane hit
+// for their parameter adjoints.  The 16
 // geometry and density slots are summed over the wave (DPP and half-wave
 // swaps) before one atomic per slot; the SH-coefficient slots, a per-ray
 // constant times one scalar per (ray, Gaussian), are staged 16 Gaussians at a
@@ -1988,10 +2068,14 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
 #pragma unroll
       for (int k = 0; k < NS; k++) { sg[k] = 0.0f; GW[k] = 0.0f; }
       int nhit = 0;
+      // a replayed tile reads the forward's per-sample sums from its record;
+      // pass A then only moves through the step's lists and marks
+      const bool from_rec = op.replay_mode == 2 && rec.ok;
 
       // pass A: the forward's per-sample sums, in the forward's order
       do {
         const bool use_marks = rec_next_marks(rec, op, M, win.count, win.kind, lane, ls.error_flag);
+        if (!from_rec)
         for_each_candidate<CAND_MARK>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
                                       [&](int j, const Gauss &g) {
         const bool want = go;
@@ -2017,6 +2101,9 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
       }, use_marks);
       } while (next_chunk(s, op, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
                             dummy_nodes, dummy_leaves, dummy_windows, rec));
+      float best = kInf;
+      if (from_rec)
+        nhit = rec_get_samples<NS>(rec, op, go, Gc0, Gc1, Gc2, sg, GW, &best, lane, ls.error_flag) ? 1 : 0;
 
       // per-sample adjoints: dL/dsigma_k (into sg) and T_k phi_k (into GW);
       // dL/dW_k is G T_k phi_k
@@ -2152,8 +2239,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
       // restart after an empty segment: from the list inside the window, else
       // through the closest-hit traversal (same decisions as the forward)
       const bool empty = go && nhit == 0;
-      float best = kInf;
-      if (op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
+      if (!from_rec && op.ess && win.kind == SRC_LIST && !win.chunked && ballot(empty)) {
         const float bmin = wave_min(empty ? b : kInf);
         for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r,
                            [&](int j, const Gauss &g) {
