@@ -439,13 +439,12 @@ __device__ __forceinline__ float wave_sum_slots16(const float *g, int lane) {
 // the ray's sum over samples of w_k T_k phi_k (zero where the ray misses b).
 // With A_c[m][r] = Y_m(d_r) G_c(r) fixed for the tile (held in registers)
 // and B[r][b] = S_b(r) staged in LDS, each channel is 16 chained 16x16x4 FP32
-// MFMAs over the 64 rays.  Operand layout of v_mfma_f32_16x16x4_f32 (wave64):
-// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
-// j + 16 (i / 4), register i % 4.  Each atomic instruction therefore adds
-// 4 floats to each of 16 Gaussians' rows: spread over 16 cache lines, the
-// atomics resolve in parallel in L2 (the transposed product, 16 consecutive
-// floats of 4 Gaussians per instruction, made the backward 3.5 % slower in
-// spite of a third of the atomic write traffic).
+// MFMAs over the 64 rays, computed transposed: D_c = B^T A_c^T, so that the
+// result holds Gaussians in rows and coefficients in columns.  Operand
+// layout of v_mfma_f32_16x16x4_f32 (wave64): first operand X[i][k] in lane
+// i + 16k, second Y[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i / 4),
+// register i % 4.  Each atomic instruction therefore adds 16 consecutive
+// floats (one 64-byte line) to each of 4 Gaussians' rows.
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kSbStride = 66;   // floats per staged row: transposed reads hit distinct banks
 
@@ -484,22 +483,23 @@ __device__ __forceinline__ void sh_batch_flush(ShBatch &B, const float *sb, floa
   f4v d0 = {0.0f, 0.0f, 0.0f, 0.0f}, d1 = d0, d2 = d0;
 #pragma unroll
   for (int q = 0; q < 16; q++) {
-    const float bv = sb[(lane & 15) * kSbStride + 4 * q + (lane >> 4)];
-    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[0][q], bv, d0, 0, 0, 0);
-    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[1][q], bv, d1, 0, 0, 0);
-    d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(B.a[2][q], bv, d2, 0, 0, 0);
+    // S_b(r) for Gaussian b = lane & 15 and ray r = 4q + (lane >> 4)
+    const float sv = sb[(lane & 15) * kSbStride + 4 * q + (lane >> 4)];
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(sv, B.a[0][q], d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(sv, B.a[1][q], d1, 0, 0, 0);
+    d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(sv, B.a[2][q], d2, 0, 0, 0);
   }
-  const int jb = __shfl(B.id, lane & 15, 64);
-  if ((lane & 15) < B.n) {
-    float *row = acc + (size_t)kAccFloats * jb + 16;
+  // lane: coefficient m = lane & 15 of Gaussians 4 (lane >> 4) + i
+  const int m = lane & 15;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int m = 4 * (lane >> 4) + i;
-      if (m < sh_k) {
-        unsafeAtomicAdd(row + m, d0[i]);
-        unsafeAtomicAdd(row + 16 + m, d1[i]);
-        unsafeAtomicAdd(row + 32 + m, d2[i]);
-      }
+  for (int i = 0; i < 4; i++) {
+    const int b = 4 * (lane >> 4) + i;
+    const int jb = __shfl(B.id, b, 64);
+    if (b < B.n && m < sh_k) {
+      float *row = acc + (size_t)kAccFloats * jb + 16;
+      unsafeAtomicAdd(row + m, d0[i]);
+      unsafeAtomicAdd(row + 16 + m, d1[i]);
+      unsafeAtomicAdd(row + 32 + m, d2[i]);
     }
   }
   __builtin_amdgcn_wave_barrier();
