@@ -124,6 +124,11 @@ typedef struct {
   int32_t no_record;         /* 1: a forward given a state keeps only its cameras and options,
                                 not its searches (the backward then searches again, with the
                                 same results); never changes results */
+  int32_t no_sample_record;  /* 1: a forward given a state records its searches but not the
+                                per-sample sums (128 B per ray segment at N_s = 8): the
+                                backward then evaluates every hit Gaussian again for them,
+                                which halves the state's pool and costs backward time; the
+                                same results up to the rounding of the colour sums */
 } rgx_render_opts;
 
 typedef struct {             /* gradient outputs, user order, float32 */
@@ -220,11 +225,12 @@ int64_t rgx_bvh_size(const rgx_bvh *bvh);
    handle can be captured into a graph once a first call has sized them).
    With empty-space skipping on (and the BVH in use) the state records each
    ray's first four closest-hit results (Alg. 1 ClosestHit, Eq. 4; 16 B per
-   ray), every window list its tiles collected, and each segment's
-   per-sample sums of density and colour (Eq. 3; 128 B per ray segment at
-   N_s = 8), in a pool of 96 KB per 64-ray tile on average; a tile that does
-   not fit is not recorded and its backward searches and sums again, with
-   the same results.  With `stats` given, the state
+   ray), every window list its tiles collected, and (unless
+   opts->no_sample_record) each segment's per-sample sums of density and
+   colour (Eq. 3; 128 B per ray segment at N_s = 8), in a pool of 48 KB per
+   64-ray tile on average, twice that with the sums; a tile that does not
+   fit is not recorded and its backward searches and sums again, with the
+   same results.  With `stats` given, the state
    also receives the totals that rgx_sync_stats returns.  Any number of states
    may be outstanding; each belongs to one forward at a time.  If the call
    fails after a new handle was made, *state still holds it: destroy it. */

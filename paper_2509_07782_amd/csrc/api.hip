@@ -351,7 +351,7 @@ static int ilog2(int v) {
 static rgx_status make_opts(rgx_context *ctx, const rgx_bvh *b, const rgx_render_opts *o,
                             MarchOpts &m) {
   if (!o) return fail(ctx, RGX_ERR_INVALID_ARG, "null opts");
-  memset(&m, 0, sizeof m);   // padding included: march_key hashes the bytes
+  memset(&m, 0, sizeof m);
   if (!(o->n_s == 1 || o->n_s == 2 || o->n_s == 4 || o->n_s == 8 || o->n_s == 16))
     return fail(ctx, RGX_ERR_UNSUPPORTED, "n_s must be 1, 2, 4, 8 or 16");
   if (o->adaptive) {
@@ -569,10 +569,13 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
     // results, every window list of every tile and each segment step's
     // per-sample sums
     const size_t need = (size_t)rays * kReplayK * sizeof(float);
-    // a shared pool: 96 KB per tile on average, at least 64 MB so that a
-    // call of few tiles with long window lists still records them all
+    // a shared pool: 48 KB per tile on average for the window lists, as much
+    // again for the per-sample sums, at least 64 MB so that a call of few
+    // tiles with long window lists still records them all
+    const bool samples = !opts->no_sample_record;
+    const size_t per_tile = (size_t)kWrecDwordsPerTile + (samples ? (size_t)kSrecDwordsPerTile : 0);
     const size_t pool = std::min<size_t>(
-        std::max<size_t>(2 + (size_t)tiles * kWrecDwordsPerTile, (size_t)1 << 24), 0xfffffff0u);
+        std::max<size_t>(2 + (size_t)tiles * per_tile, (size_t)1 << 24), 0xfffffff0u);
     if (m.ess && !m.brute_force && !opts->no_record && grow_record(f, f->replay, need) &&
         grow_record(f, f->wrec, pool * sizeof(uint32_t)) &&
         grow_record(f, f->wrec_tile, (size_t)tiles * 2 * sizeof(uint32_t))) {
@@ -581,6 +584,7 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
       m.wrec = (uint32_t *)f->wrec.p;
       m.wrec_tile = (uint32_t *)f->wrec_tile.p;
       m.wrec_cap = (uint32_t)pool;
+      m.sample_rec = samples ? 1 : 0;
       // the pool's 64-bit allocation counter (dwords 0-1) starts past itself
       // (fill kernels, not memset nodes, so the call can be captured)
       hipError_t e = launch_fill(f->wrec.p, 1, 2u, stream);
@@ -639,6 +643,7 @@ rgx_status rgx_render_backward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_f
     m.wrec = (uint32_t *)f->wrec.p;
     m.wrec_tile = (uint32_t *)f->wrec_tile.p;
     m.wrec_cap = (uint32_t)std::min<size_t>(f->wrec.bytes / sizeof(uint32_t), 0xfffffff0u);
+    m.sample_rec = f->opts.no_sample_record ? 0 : 1;
     ctx->replayed = 1;
   }
   BwdIn in;

@@ -76,6 +76,7 @@ struct MarchOpts {
   uint32_t *wrec;         // window-list record pool: [0,2) 64-bit allocation counter, records after
   uint32_t *wrec_tile;    // per tile of the call: (complete, first chunk offset)
   uint32_t wrec_cap;      // pool size in dwords
+  int32_t sample_rec;     // the record also holds each segment step's per-sample sums
 };
 constexpr int kReplayK = 4;
 // Window-list record: every collection of a tile appends one chunk to a
@@ -91,8 +92,10 @@ constexpr uint32_t kWrecNone = 0xffffffffu;
 // colour sum W_k (4 N_S floats per lane, stored as [k][component][lane rank]),
 // then for the lanes whose segment was empty the restart distance it found.
 constexpr int kSrecHeader = 5;
-// pool size per tile of the call (average): window lists and sample records
-constexpr int kWrecDwordsPerTile = 24576;
+// pool size per tile of the call (average): window lists, and with them the
+// sample records
+constexpr int kWrecDwordsPerTile = 12288;
+constexpr int kSrecDwordsPerTile = 12288;
 
 // Scalar (constant address space) views of read-only scene data: a
 // wave-uniform address loads once into SGPRs for the whole wave.

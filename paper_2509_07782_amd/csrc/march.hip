@@ -1874,7 +1874,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         });
       }
       // the step's per-sample sums and restarts, for a replaying backward
-      if (op.replay_mode == 1)
+      if (op.replay_mode == 1 && op.sample_rec)
         rec_put_samples<NS>(rec, op, go && nhit > 0, empty, best, sg, W0, W1, W2, lane);
       if (go) {
         if (nhit > 0) {
@@ -2070,7 +2070,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
       int nhit = 0;
       // a replayed tile reads the forward's per-sample sums from its record;
       // pass A then only moves through the step's lists and marks
-      const bool from_rec = op.replay_mode == 2 && rec.ok;
+      const bool from_rec = op.replay_mode == 2 && rec.ok && op.sample_rec;
 
       // pass A: the forward's per-sample sums, in the forward's order
       do {

@@ -49,7 +49,8 @@ class RenderOpts(C.Structure):
                 ("t_eps", C.c_float), ("ess", C.c_int32), ("brute_force", C.c_int32),
                 ("ray_order", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
                 ("persistent", C.c_int32), ("window_segments", C.c_int32),
-                ("bg", C.c_float * 3), ("no_record", C.c_int32)]
+                ("bg", C.c_float * 3), ("no_record", C.c_int32),
+                ("no_sample_record", C.c_int32)]
 
 
 class Grads(C.Structure):
@@ -173,6 +174,7 @@ def make_opts(o) -> RenderOpts:
     for i in range(3):
         r.bg[i] = float(o.bg[i])
     r.no_record = int(bool(getattr(o, "no_record", False)))
+    r.no_sample_record = int(bool(getattr(o, "no_sample_record", False)))
     return r
 
 

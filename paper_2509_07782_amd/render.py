@@ -33,6 +33,7 @@ class RenderOptions:
     window_segments: int = 1
     bg: tuple = (0.0, 0.0, 0.0)
     no_record: bool = False
+    no_sample_record: bool = False
 
 
 def _keys(params: dict):

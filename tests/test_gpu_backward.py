@@ -124,6 +124,17 @@ def test_forward_state_replay(small_setup, torch_cuda):
         assert not r.ctx.backward_replayed()
         for k in PARAM_KEYS:
             assert _rel(gref[k], g_own[k]) <= 1e-5, k
+    # a state without the per-sample sums replays the searches and evaluates
+    # the Gaussians again for the sums: the same gradients up to the rounding
+    # of the colour sums
+    o_ns = _opts(adaptive=True, ess=1, t_eps=1e-4, no_sample_record=True)
+    rgb3, T3 = r.forward([cam], o_ns, state=s3)
+    assert torch.equal(rgb3, rgb) and torch.equal(T3, T)
+    g_ns = r.backward(s3, rgb3, T3, gCt, None, params)
+    torch.cuda.synchronize()
+    assert r.ctx.backward_replayed()
+    for k in PARAM_KEYS:
+        assert _rel(g_rep[k], g_ns[k]) <= 1e-5, k
     # a rebuild (same parameters, new build) makes the state stale
     r.forward([cam], o, state=s1)
     r.build(params, sc["sh_degree"], force=True)
@@ -178,9 +189,10 @@ def test_autograd_stale_structure_rebuilds(small_setup, torch_cuda):
 
 def test_window_replay_dense_chunked(torch_cuda):
     """A dense cluster whose windows overflow the 512-entry list, so segments
-    run in Z chunks and some tiles may not fit their record region: the
-    replayed backward (recorded chunks, earlier chunks of a segment re-read for
-    pass B) equals the backward that walks the tree itself."""
+    run in Z chunks: the replayed backward (recorded chunks and per-sample
+    sums, earlier chunks of a segment re-read for pass B), with or without the
+    per-sample sums in the record, equals the backward that walks the tree
+    itself."""
     torch = torch_cuda
     sc = inputs.make_scene("cluster", 60000, 77)
     sc["log_scales"] = sc["log_scales"] + 0.8       # larger Gaussians: long lists
@@ -211,6 +223,16 @@ def test_window_replay_dense_chunked(torch_cuda):
     assert not r.ctx.backward_replayed()
     for k in PARAM_KEYS:
         a, b = g_rep[k].cpu().numpy(), g_own[k].cpu().numpy()
+        d = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert d <= 1e-5, (k, d)
+    rgb3, T3 = r.forward([cam], _opts(adaptive=True, ess=1, t_eps=1e-4, window_segments=4,
+                                      no_sample_record=True), state=s2)
+    assert torch.equal(rgb3, rgb) and torch.equal(T3, T)
+    g_ns = r.backward(s2, rgb3, T3, gCt, None, params)
+    torch.cuda.synchronize()
+    assert r.ctx.backward_replayed()
+    for k in PARAM_KEYS:
+        a, b = g_ns[k].cpu().numpy(), g_own[k].cpu().numpy()
         d = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
         assert d <= 1e-5, (k, d)
     assert r.ctx.error_flags() == 0
