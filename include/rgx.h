@@ -381,6 +381,15 @@ rgx_status rgx_kernel_times(rgx_context *ctx, double *ms, int64_t *launches, int
    recorded searches, 0 if the state held no record and it searched itself. */
 int32_t rgx_backward_replayed(const rgx_context *ctx);
 
+/* (host) Caps the record pool of every later forward given a state on this
+   context at max_bytes (0: no cap beyond the default sizing, which is 96 KB
+   per 64-ray tile, at least 64 MB, at most 16 GiB).  Tiles whose records do
+   not fit are not recorded (RGX_TOT_UNRECORDED counts them) and their
+   backward searches and sums again, with the same results, so a cap trades
+   backward time for device memory and never changes results.
+   RGX_ERR_INVALID_ARG for a negative max_bytes. */
+rgx_status rgx_set_record_limit(rgx_context *ctx, int64_t max_bytes);
+
 const char *rgx_status_string(rgx_status s);
 const char *rgx_last_error(const rgx_context *ctx);
 

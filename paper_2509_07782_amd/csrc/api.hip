@@ -51,6 +51,7 @@ struct rgx_context {
   uint64_t build_serial = 0;        // bumped by every build on the context: names a structure build
   int32_t replayed = 0;             // whether the last backward replayed
   double *iso_scratch = nullptr;    // device address of the fixed loss workspace on this device
+  int64_t record_limit = 0;         // cap on a forward state's record pool in bytes (0: none)
 };
 
 // Records hipEvents on `stream` around `launch` when timing is enabled.
@@ -574,8 +575,11 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
     // tiles with long window lists still records them all
     const bool samples = !opts->no_sample_record;
     const size_t per_tile = (size_t)kWrecDwordsPerTile + (samples ? (size_t)kSrecDwordsPerTile : 0);
-    const size_t pool = std::min<size_t>(
+    size_t pool = std::min<size_t>(
         std::max<size_t>(2 + (size_t)tiles * per_tile, (size_t)1 << 24), 0xfffffff0u);
+    // a caller's cap (the two counter dwords always fit)
+    if (ctx->record_limit > 0)
+      pool = std::max<size_t>(std::min<size_t>(pool, (size_t)ctx->record_limit / sizeof(uint32_t)), 2);
     if (m.ess && !m.brute_force && !opts->no_record && grow_record(f, f->replay, need) &&
         grow_record(f, f->wrec, pool * sizeof(uint32_t)) &&
         grow_record(f, f->wrec_tile, (size_t)tiles * 2 * sizeof(uint32_t))) {
@@ -787,6 +791,13 @@ rgx_status rgx_bvh_debug(rgx_context *ctx, const rgx_bvh *b, uint64_t *keys, int
     HIP_TRY(ctx, hipMemcpy(&c, b->counters.p, 4, hipMemcpyDeviceToHost));
     *n_active = c;
   }
+  return RGX_OK;
+}
+
+rgx_status rgx_set_record_limit(rgx_context *ctx, int64_t max_bytes) {
+  if (!ctx) return RGX_ERR_INVALID_ARG;
+  if (max_bytes < 0) return fail(ctx, RGX_ERR_INVALID_ARG, "negative record limit");
+  ctx->record_limit = max_bytes;
   return RGX_OK;
 }
 

@@ -70,7 +70,7 @@ EXPORTS = ("rgx_create", "rgx_destroy", "rgx_build_bvh", "rgx_bvh_destroy", "rgx
            "rgx_false_positives", "rgx_dump_hits", "rgx_bvh_debug",
            "rgx_error_flags", "rgx_set_kernel_timing", "rgx_kernel_times", "rgx_isotropic_loss",
            "rgx_isotropic_loss_noalloc", "rgx_adam_step",
-           "rgx_backward_replayed", "rgx_status_string", "rgx_last_error")
+           "rgx_backward_replayed", "rgx_status_string", "rgx_last_error", "rgx_set_record_limit")
 
 KERNEL_KINDS = ("build", "forward", "backward", "finalize")   # RGX_KERN_* order
 
@@ -127,6 +127,8 @@ def load():
     L.rgx_kernel_times.restype = st
     L.rgx_backward_replayed.argtypes = [vp]
     L.rgx_backward_replayed.restype = C.c_int32
+    L.rgx_set_record_limit.argtypes = [vp, C.c_int64]
+    L.rgx_set_record_limit.restype = st
     L.rgx_status_string.argtypes = [st]
     L.rgx_status_string.restype = C.c_char_p
     L.rgx_last_error.argtypes = [vp]
@@ -209,6 +211,10 @@ class Context:
         ms, cnt = (C.c_double * n)(), (C.c_int64 * n)()
         check(load().rgx_kernel_times(self.h, ms, cnt, int(bool(reset))), self.h, "kernel_times")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    def set_record_limit(self, max_bytes: int):
+        """Caps the record pool of later forwards given a state (0: no cap)."""
+        check(load().rgx_set_record_limit(self.h, int(max_bytes)), self.h, "set_record_limit")
 
     def backward_replayed(self) -> bool:
         """Whether the last backward replayed its forward's closest-hit results."""

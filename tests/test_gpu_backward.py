@@ -239,6 +239,50 @@ def test_window_replay_dense_chunked(torch_cuda):
     r.close()
 
 
+def test_record_limit_mixes_replayed_and_searched_tiles(torch_cuda):
+    """A capped record pool leaves the tiles whose records do not fit
+    unrecorded: their backward searches and sums again while the other tiles
+    replay.  Images are unchanged and the gradients equal those of a backward
+    that searches every tile itself."""
+    torch = torch_cuda
+    sc = inputs.make_scene("cluster", 20000, 41)
+    cam = inputs.look_at_camera(64, 48, (0.9, 0.3, 2.2), fov_deg=50.0)
+    tiles = (64 // 8) * (48 // 8)
+    r, params = renderer_for(sc)
+    o = _opts(adaptive=True, ess=1, t_eps=1e-4)
+    rng = np.random.default_rng(8)
+    gCt = torch.from_numpy(rng.standard_normal((cam.width * cam.height, 3)).astype(np.float32)).cuda()
+    s_own, st = r.new_state(), r.new_state()
+    rgb, T = r.forward([cam], _opts(adaptive=True, ess=1, t_eps=1e-4, no_record=True), state=s_own)
+    g_own = r.backward(s_own, rgb, T, gCt, None, params)
+    torch.cuda.synchronize()
+    seen = []
+    mixed = False
+    for limit in [1 << k for k in range(22, 9, -1)]:
+        r.ctx.set_record_limit(limit)
+        rgb2, T2, _ = r.forward([cam], o, stats=True, state=st)
+        torch.cuda.synchronize()
+        assert torch.equal(rgb2, rgb) and torch.equal(T2, T)
+        unrec = st.totals()["unrecorded"]
+        seen.append((limit, unrec))
+        if 0 < unrec < tiles:
+            g = r.backward(st, rgb2, T2, gCt, None, params)
+            torch.cuda.synchronize()
+            assert r.ctx.backward_replayed()
+            for k in PARAM_KEYS:
+                assert _rel(g[k], g_own[k]) <= 1e-5, (k, limit)
+            mixed = True
+            break
+    r.ctx.set_record_limit(0)
+    with pytest.raises(Exception):
+        r.ctx.set_record_limit(-1)
+    assert mixed, seen
+    assert r.ctx.error_flags() == 0
+    for s_ in (s_own, st):
+        s_.close()
+    r.close()
+
+
 def test_backward_bvh_equals_brute_force(small_setup, torch_cuda):
     sc, cam, r, params, gC, gT = small_setup
     a = _gpu_grads(torch_cuda, r, cam, _opts(dt=0.005, brute_force=True), params, gC, gT)
