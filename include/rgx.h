@@ -294,9 +294,9 @@ rgx_status rgx_dump_hits(rgx_context *ctx, const rgx_bvh *bvh, const rgx_camera 
      nodes [max(n-1,1), 16] float internal nodes: left box lo/hi, right box lo/hi,
            children as int bits (>= 0 internal, < 0 leaf ~i, INT32_MIN none) in
            words 3 and 7, the node's first and last leaf index in words 11 and 15
-     nodes4 [max(n-1,1), 36] float 4-wide records, defined at the binary
-           internal nodes of even depth (the root has depth 0; other rows are
-           unspecified): 4 child boxes (lo xyz, hi xyz) in words 0..23, 4
+     nodes4 [max(n-1,1), 36] float 4-wide records, one per binary internal
+           node (row = its index; the walk from row 0 reaches those it needs):
+           4 child boxes (lo xyz, hi xyz) in words 0..23, 4
            child links as int bits in words 24..27 (>= 0 a 4-wide record, < 0
            leaf ~i, INT32_MIN none), 4 (first, last) leaf ranges in 28..35
      n_active (host) number of active Gaussians. */

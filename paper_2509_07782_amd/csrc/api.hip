@@ -88,7 +88,7 @@ struct rgx_bvh {
   int sorted_sel = 0;
   uint64_t serial = 0;              // the context's build serial of the current contents
   DevBuf geom_user, aabb_user, aux_user, aux, active, bounds, counters, keys0, keys1, vals0, vals1, hist, geom,
-      aabb, col, nodes, nodes4, seg, parent, acc, zsum, sg_user, sgrec, sgacc;
+      aabb, col, nodes, nodes4, seg, acc, zsum, sg_user, sgrec, sgacc;
 };
 
 // Forward state: what one forward rendered and what its searches found.
@@ -206,7 +206,7 @@ void rgx_bvh_destroy(rgx_bvh *b) {
   if (!b) return;
   DevBuf *all[] = {&b->geom_user, &b->aabb_user, &b->aux_user, &b->aux, &b->active, &b->bounds, &b->counters, &b->keys0,
                    &b->keys1, &b->vals0, &b->vals1, &b->hist, &b->geom, &b->aabb, &b->col,
-                   &b->nodes, &b->nodes4, &b->seg, &b->parent, &b->acc, &b->zsum,
+                   &b->nodes, &b->nodes4, &b->seg, &b->acc, &b->zsum,
                    &b->sg_user, &b->sgrec, &b->sgacc};
   for (DevBuf *d : all) release(*d);
   delete b;
@@ -266,7 +266,6 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   int64_t P = 1;
   while (P < n) P <<= 1;
   ENS(seg, (size_t)(2 * P) * 6 * 4);
-  ENS(parent, (size_t)(2 * n) * 4);
   ENS(acc, (size_t)n * kAccFloats * 4);
   if (g->n_sg > 0) {
     ENS(sg_user, (size_t)n * kSgFloats * 4);
@@ -307,7 +306,6 @@ rgx_status rgx_build_bvh(rgx_context *ctx, const rgx_gaussians *g, const rgx_bui
   a.geom = (float *)b->geom.p; a.aabb = (float *)b->aabb.p; a.col = (float *)b->col.p;
   a.nodes = (float *)b->nodes.p; a.seg = (float *)b->seg.p;
   a.nodes4 = (float *)b->nodes4.p;
-  a.parent = (int32_t *)b->parent.p;
   e = timed(ctx, RGX_KERN_BUILD, stream, [&] {
     hipError_t r = launch_build(a, stream);
     if (r == hipSuccess) r = launch_fill(b->acc.p, n * kAccFloats, 0u, stream);

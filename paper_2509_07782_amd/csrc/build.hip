@@ -353,13 +353,11 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
                                                         const uint64_t *__restrict__ keys,
                                                         const float *__restrict__ aabb,
                                                         const float *__restrict__ seg, int64_t P,
-                                                        float4 *__restrict__ nodes,
-                                                        int32_t *__restrict__ parent) {
+                                                        float4 *__restrict__ nodes) {
   const int n = counters[0];
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= n_max) return;
   const int i = (int)tid;
-  // parent[0 .. n-2] internal nodes, parent[n-1 .. 2n-2] leaves
   if (n == 1 && i == 0) {
     nodes[0] = make_float4(aabb[0], aabb[1], aabb[2], __int_as_float(~0));
     nodes[1] = make_float4(aabb[3], aabb[4], aabb[5], __int_as_float(kNoChild));
@@ -368,7 +366,6 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
     return;
   }
   if (i >= n - 1) return;
-  if (i == 0) parent[0] = -1;
   const int d = (lcp(keys, n, i, i + 1) - lcp(keys, n, i, i - 1)) >= 0 ? 1 : -1;
   const int dmin = lcp(keys, n, i, i - d);
   int64_t lmax = 2;
@@ -390,8 +387,6 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
   const int lo = i < j ? i : j, hi = i < j ? j : i;
   const int left = (lo == gamma) ? ~gamma : gamma;
   const int right = (hi == gamma + 1) ? ~(gamma + 1) : gamma + 1;
-  if (left < 0) parent[(n - 1) + gamma] = i; else parent[left] = i;
-  if (right < 0) parent[(n - 1) + gamma + 1] = i; else parent[right] = i;
   float bl[6], br[6];
   seg_query(seg, P, lo, gamma, bl);
   seg_query(seg, P, gamma + 1, hi, br);
@@ -404,26 +399,50 @@ __global__ __launch_bounds__(256) void k_lbvh_hierarchy(int64_t n_max,
   nd[3] = make_float4(br[3], br[4], br[5], __int_as_float(hi));
 }
 
-// 4-wide nodes: every binary internal node at even depth (the root at depth
-// 0) gathers its children, and the children of those of them that are
-// internal (odd depth), into one record of up to 4 child boxes, links and
-// leaf ranges, in left-to-right (Z) order.  Records keep the binary node
-// index, so a link to an internal child is that child's binary index.
+// 4-wide nodes by surface-area collapse: every binary internal node gathers
+// its two children and then, while it has fewer than four, replaces the
+// internal child of largest box surface area by that child's two children
+// (in place, so the record stays in left-to-right Z order).  Every internal
+// node gets a record, indexed by its binary index, so a link to an internal
+// child is that child's binary index.
 __global__ __launch_bounds__(256) void k_bvh4(int64_t n_max, const int32_t *__restrict__ counters,
                                               const float4 *__restrict__ nodes,
-                                              const int32_t *__restrict__ parent,
                                               float *__restrict__ nodes4) {
   const int n = counters[0];
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int n_inner = n > 1 ? n - 1 : 1;
   if (tid >= n_max || n <= 0 || tid >= n_inner) return;
   const int i = (int)tid;
-  int odd = 0;
-  for (int x = i, steps = 0; x > 0 && steps <= n; steps++) {
-    x = parent[x];
-    odd ^= 1;
+  int lk[4];
+  float4 blo[4], bhi[4];
+  int m = 0;
+  {
+    const float4 a = nodes[4 * (size_t)i], b = nodes[4 * (size_t)i + 1], c = nodes[4 * (size_t)i + 2],
+                 d = nodes[4 * (size_t)i + 3];
+    const int l0 = __float_as_int(a.w), l1 = __float_as_int(b.w);
+    if (l0 != kNoChild) { lk[m] = l0; blo[m] = a; bhi[m] = b; m++; }
+    if (l1 != kNoChild) { lk[m] = l1; blo[m] = c; bhi[m] = d; m++; }
   }
-  if (odd) return;
+  while (m < 4) {
+    int best = -1;
+    float bsa = -1.0f;
+    for (int k = 0; k < m; k++) {
+      if (lk[k] < 0 || lk[k] >= n_inner) continue;
+      const float dx = bhi[k].x - blo[k].x, dy = bhi[k].y - blo[k].y, dz = bhi[k].z - blo[k].z;
+      const float sa = dx * dy + dy * dz + dz * dx;
+      if (sa > bsa) { bsa = sa; best = k; }
+    }
+    if (best < 0) break;
+    const int x = lk[best];
+    const float4 a = nodes[4 * (size_t)x], b = nodes[4 * (size_t)x + 1], c = nodes[4 * (size_t)x + 2],
+                 d = nodes[4 * (size_t)x + 3];
+    const int l0 = __float_as_int(a.w), l1 = __float_as_int(b.w);
+    if (l0 == kNoChild || l1 == kNoChild) break;   // only the root of a one-leaf tree has one child
+    for (int k = m; k > best + 1; k--) { lk[k] = lk[k - 1]; blo[k] = blo[k - 1]; bhi[k] = bhi[k - 1]; }
+    lk[best] = l0; blo[best] = a; bhi[best] = b;
+    lk[best + 1] = l1; blo[best + 1] = c; bhi[best + 1] = d;
+    m++;
+  }
   float f[kNode4Floats];
   for (int k = 0; k < 24; k++) f[k] = 0.0f;
   for (int k = 0; k < 4; k++) {
@@ -431,39 +450,17 @@ __global__ __launch_bounds__(256) void k_bvh4(int64_t n_max, const int32_t *__re
     f[28 + 2 * k] = __int_as_float(1);        // empty range
     f[29 + 2 * k] = __int_as_float(0);
   }
-  int m = 0;
-  auto add = [&](int link, float lx, float ly, float lz, float hx, float hy, float hz, int first,
-                 int last) {
-    f[6 * m + 0] = lx; f[6 * m + 1] = ly; f[6 * m + 2] = lz;
-    f[6 * m + 3] = hx; f[6 * m + 4] = hy; f[6 * m + 5] = hz;
-    f[24 + m] = __int_as_float(link);
-    f[28 + 2 * m] = __int_as_float(first);
-    f[29 + 2 * m] = __int_as_float(last);
-    m++;
-  };
-  const float4 a = nodes[4 * (size_t)i], b = nodes[4 * (size_t)i + 1], c = nodes[4 * (size_t)i + 2],
-               d = nodes[4 * (size_t)i + 3];
-  for (int side = 0; side < 2; side++) {
-    const int link = __float_as_int(side ? b.w : a.w);
-    if (link == kNoChild) continue;
-    const float4 lo = side ? c : a, hi = side ? d : b;
-    if (link < 0) {
-      add(link, lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, ~link, ~link);
-      continue;
+  for (int k = 0; k < m; k++) {
+    f[6 * k + 0] = blo[k].x; f[6 * k + 1] = blo[k].y; f[6 * k + 2] = blo[k].z;
+    f[6 * k + 3] = bhi[k].x; f[6 * k + 4] = bhi[k].y; f[6 * k + 5] = bhi[k].z;
+    f[24 + k] = __int_as_float(lk[k]);
+    int first = ~lk[k], last = ~lk[k];
+    if (lk[k] >= 0) {
+      first = __float_as_int(nodes[4 * (size_t)lk[k] + 2].w);
+      last = __float_as_int(nodes[4 * (size_t)lk[k] + 3].w);
     }
-    const float4 a2 = nodes[4 * (size_t)link], b2 = nodes[4 * (size_t)link + 1],
-                 c2 = nodes[4 * (size_t)link + 2], d2 = nodes[4 * (size_t)link + 3];
-    for (int side2 = 0; side2 < 2; side2++) {
-      const int l2 = __float_as_int(side2 ? b2.w : a2.w);
-      if (l2 == kNoChild) continue;
-      const float4 lo2 = side2 ? c2 : a2, hi2 = side2 ? d2 : b2;
-      int first = ~l2, last = ~l2;
-      if (l2 >= 0) {
-        first = __float_as_int(nodes[4 * (size_t)l2 + 2].w);
-        last = __float_as_int(nodes[4 * (size_t)l2 + 3].w);
-      }
-      add(l2, lo2.x, lo2.y, lo2.z, hi2.x, hi2.y, hi2.z, first, last);
-    }
+    f[28 + 2 * k] = __int_as_float(first);
+    f[29 + 2 * k] = __int_as_float(last);
   }
   float4 *out = reinterpret_cast<float4 *>(nodes4 + (size_t)kNode4Floats * i);
   for (int k = 0; k < kNode4Floats / 4; k++)
@@ -515,9 +512,9 @@ hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
   for (int64_t lo = P >> 1; lo >= 1; lo >>= 1)
     k_seg_level<<<nblk(lo, 256), 256, 0, st>>>(lo, 2 * lo, a.seg);
   k_lbvh_hierarchy<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, a.keys[cur], a.aabb, a.seg, P,
-                                                 reinterpret_cast<float4 *>(a.nodes), a.parent);
+                                                 reinterpret_cast<float4 *>(a.nodes));
   k_bvh4<<<nblk(n, 256), 256, 0, st>>>(n, a.counters, reinterpret_cast<const float4 *>(a.nodes),
-                                       a.parent, a.nodes4);
+                                       a.nodes4);
   return hipGetLastError();
 }
 

@@ -26,9 +26,8 @@ struct BuildArgs {
   int *sorted_sel;           // (host) which ping-pong buffer holds the result
   // outputs (Z order)
   float *geom, *aabb, *col, *aux, *nodes;
-  float *nodes4;             // 4-wide nodes, indexed like the binary nodes (even depths)
+  float *nodes4;             // 4-wide nodes, one per binary internal node, same index
   float *seg;                // segment tree of leaf boxes, 2P boxes
-  int32_t *parent;
 };
 hipError_t launch_build(const BuildArgs &a, hipStream_t st);
 int64_t iso_blocks(int64_t n);
@@ -45,7 +44,7 @@ struct SceneDev {
   const float *geom;          // [n,16]
   const float *col;           // [n,col_stride]
   const float *nodes;         // [max(n-1,1),16]
-  const float *nodes4;        // [max(n-1,1),36] 4-wide nodes at even binary depth
+  const float *nodes4;        // [max(n-1,1),36] 4-wide nodes, one per binary internal node
   const float *aabb;          // [n,6]
   const int32_t *counters;    // [0] = active count
   const uint32_t *perm;       // Z index -> user index

@@ -173,27 +173,34 @@ __device__ __forceinline__ void sg_colour(const float *sg, int j, float dx, floa
   }
 }
 
-// Wave-uniform DFS stack, entry i held by lane i % 64 of s0, s1 or s2.  The
-// closest-hit walk over the 4-wide records pushes at most 3 entries per
-// record on its path.  Binary internal nodes lie at most 86 levels deep (the
-// Karras split positions grow strictly down the tree over the 63-bit key
-// extended by a 23-bit index), so a path meets at most 44 4-wide records and
-// the stack never holds more than 132 entries: 192 always suffice.
+// Wave-uniform DFS stack, entry i held by lane i % 64 of s0 .. s4.  The
+// closest-hit walk pushes at most 3 entries per 4-wide record on its current
+// path (the record's unvisited children).  The records sit at binary internal
+// nodes, each strictly deeper than the one before it on a path, and binary
+// internal nodes lie at most 86 levels deep (the Karras split positions grow
+// strictly down the tree over the 63-bit key extended by a 23-bit index), so
+// a path meets at most 87 records and the stack never holds more than 261
+// entries: 320 always suffice.
 struct WaveStack {
-  int s0 = 0, s1 = 0, s2 = 0, sp = 0, lane = 0;
+  int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, sp = 0, lane = 0;
   __device__ __forceinline__ bool push(int v) {
     if (sp < 64) s0 = lane == sp ? v : s0;
     else if (sp < 128) s1 = lane == sp - 64 ? v : s1;
     else if (sp < 192) s2 = lane == sp - 128 ? v : s2;
+    else if (sp < 256) s3 = lane == sp - 192 ? v : s3;
+    else if (sp < 320) s4 = lane == sp - 256 ? v : s4;
     else return false;
     sp++;
     return true;
   }
   __device__ __forceinline__ int pop() {
     sp--;
-    return sp < 64 ? __builtin_amdgcn_readlane(s0, sp)
-                   : sp < 128 ? __builtin_amdgcn_readlane(s1, sp - 64)
-                              : __builtin_amdgcn_readlane(s2, sp - 128);
+    const int q = sp >> 6, l = sp & 63;
+    return q == 0 ? __builtin_amdgcn_readlane(s0, l)
+         : q == 1 ? __builtin_amdgcn_readlane(s1, l)
+         : q == 2 ? __builtin_amdgcn_readlane(s2, l)
+         : q == 3 ? __builtin_amdgcn_readlane(s3, l)
+                  : __builtin_amdgcn_readlane(s4, l);
   }
 };
 
