@@ -228,7 +228,8 @@ int64_t rgx_bvh_size(const rgx_bvh *bvh);
    ray), every window list its tiles collected, and (unless
    opts->no_sample_record) each segment's per-sample sums of density and
    colour (Eq. 3; 128 B per ray segment at N_s = 8), in a pool of 48 KB per
-   64-ray tile on average, twice that with the sums; a tile that does not
+   64-ray tile on average, twice that with the sums (three times at N_s =
+   16); a tile that does not
    fit is not recorded and its backward searches and sums again, with the
    same results.  With `stats` given, the state
    also receives the totals that rgx_sync_stats returns.  Any number of states
@@ -383,7 +384,7 @@ int32_t rgx_backward_replayed(const rgx_context *ctx);
 
 /* (host) Caps the record pool of every later forward given a state on this
    context at max_bytes (0: no cap beyond the default sizing, which is 96 KB
-   per 64-ray tile, at least 64 MB, at most 16 GiB).  Tiles whose records do
+   per 64-ray tile at N_s <= 8, at least 64 MB, at most 16 GiB).  Tiles whose records do
    not fit are not recorded (RGX_TOT_UNRECORDED counts them) and their
    backward searches and sums again, with the same results, so a cap trades
    backward time for device memory and never changes results.

@@ -569,10 +569,12 @@ rgx_status rgx_render_forward(rgx_context *ctx, const rgx_bvh *bvh, const rgx_ca
     // per-sample sums
     const size_t need = (size_t)rays * kReplayK * sizeof(float);
     // a shared pool: 48 KB per tile on average for the window lists, as much
-    // again for the per-sample sums, at least 64 MB so that a call of few
-    // tiles with long window lists still records them all
+    // again for the per-sample sums at N_s <= 8 (twice that at 16), at least
+    // 64 MB so that a call of few tiles with long window lists still records
+    // them all
     const bool samples = !opts->no_sample_record;
-    const size_t per_tile = (size_t)kWrecDwordsPerTile + (samples ? (size_t)kSrecDwordsPerTile : 0);
+    const size_t per_tile = (size_t)kWrecDwordsPerTile +
+                            (samples ? (size_t)kSrecDwordsPerTile * (m.n_s > 8 ? 2 : 1) : 0);
     size_t pool = std::min<size_t>(
         std::max<size_t>(2 + (size_t)tiles * per_tile, (size_t)1 << 24), 0xfffffff0u);
     // a caller's cap (the two counter dwords always fit)
