@@ -213,6 +213,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": dom_bytes},
+        # both march kernels against the same roofline (the object above is
+        # the dominant one's)
+        "roofline_by_kernel": {
+            k: {"ms": kern_ms[k], "algorithmic_bytes": b, "achieved": b / (kern_ms[k] * 1e-3) / 1e9,
+                "frac": b / (kern_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            for k, b in (("forward", fwd_bytes), ("backward", bwd_bytes)) if kern_ms.get(k)},
     }
     if not args.no_side:
         # free the headline workload's buffers before the larger scenes
