@@ -17,7 +17,7 @@ import torch
 
 from .render import RenderOptions, Renderer
 
-TILES = ((8, 8), (16, 4), (4, 16), (32, 2))
+TILES = ((8, 8), (16, 4), (4, 16), (32, 2), (64, 1))
 WINDOWS = (1, 2, 4)
 
 _CACHE: dict = {}
