@@ -179,11 +179,25 @@ def main():
     dom_bytes = bwd_bytes if dom == "backward" else fwd_bytes
     achieved = dom_bytes / (kern_ms[dom] * 1e-3) / 1e9
     traffic = None
+    valu = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         t = json.load(open(tfile))
         if t.get("source_hash") == source_hash() and dom in t.get("by_role", {}):
-            traffic = t["by_role"][dom]["bytes_per_launch"]
+            role = t["by_role"][dom]
+            traffic = role["bytes_per_launch"]
+            if "valu_insts_per_launch" in role:
+                # VALU issue against the chip's: 1024 SIMDs, one wave64 VALU
+                # instruction per 4 cycles each, at the 2.4 GHz peak clock;
+                # the counter run's busy cycles give the clock the kernel
+                # actually ran at
+                ins = role["valu_insts_per_launch"]
+                peak = 1024 * 2.4e9 / 4
+                valu = {"bound": "alu", "kernel": dom, "unit": "wave64 VALU instructions/s",
+                        "achieved": ins / (kern_ms[dom] * 1e-3), "peak": peak,
+                        "frac": ins / (kern_ms[dom] * 1e-3) / peak,
+                        "clock_ghz": role["busy_cycles_per_launch"] / (kern_ms[dom] * 1e-3) / 1e9,
+                        "source": "rocprofv3 SQ_INSTS_VALU, SQ_BUSY_CYCLES (profiles/)"}
     out = {
         "metric": "Mrays/s fwd and fwd+bwd at 1M Gaussians; ms per 1920x1080 frame",
         "value": R / (ms_step * 1e-3) / 1e6,
@@ -213,6 +227,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": dom_bytes},
+        "roofline_alu": valu,
         # both march kernels against the same roofline (the object above is
         # the dominant one's)
         "roofline_by_kernel": {
