@@ -392,18 +392,21 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
-// Minimum over the wave without LDS traffic: in-row DPP permutes (quad xor
-// 1, quad xor 2, half-row mirror, row mirror) leave each row's minimum in
-// every lane of the row; the four rows are then read back.
-__device__ __forceinline__ float wave_min_dpp(float v) {
-  v = fminf(v, dpp<0xb1>(v));
-  v = fminf(v, dpp<0x4e>(v));
-  v = fminf(v, dpp<0x141>(v));
-  v = fminf(v, dpp<0x140>(v));
-  auto rl = [&](int l) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-  };
-  return fminf(fminf(rl(0), rl(16)), fminf(rl(32), rl(48)));
+// Minimum over the wave of values that are never negative (+inf allowed;
+// -0 counts as 0), without LDS traffic: the bit patterns of such floats
+// order as signed integers, so each in-row DPP permute (quad xor 1, quad
+// xor 2, half-row mirror, row mirror) is one fused integer minimum, leaving
+// each row's minimum in every lane of the row; the four rows are then read
+// back.
+__device__ __forceinline__ float wave_min_nonneg_dpp(float v) {
+  int x = __float_as_int(v);
+  x = min(x, __builtin_amdgcn_update_dpp(0x7fffffff, x, 0xb1, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x4e, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x141, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x140, 0xf, 0xf, false));
+  const int a = min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16));
+  const int b = min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48));
+  return __int_as_float(min(a, b));
 }
 
 
@@ -592,7 +595,7 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
         link[k] = __float_as_int(f[24 + k]);
         const bool valid = link[k] != kNoChild;
         bad = bad || (valid && (link[k] >= 0 ? link[k] >= n_inner : ~link[k] >= n_active));
-        e[k] = valid ? wave_min_dpp(box_entry(f[6 * k], f[6 * k + 1], f[6 * k + 2], f[6 * k + 3],
+        e[k] = valid ? wave_min_nonneg_dpp(box_entry(f[6 * k], f[6 * k + 1], f[6 * k + 2], f[6 * k + 3],
                                               f[6 * k + 4], f[6 * k + 5], r, lo, hi))
                      : kInf;
       }
