@@ -1309,17 +1309,17 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
       const uint64_t bits0 = ballot(keep);
       if (!bits0) continue;
       const Gauss mine = with_origin(load_gauss_lane(s.geom, keep ? id : 0), ox, oy, oz);
-      bool hit_mine = false;
+      uint64_t hits = 0;   // (uniform) the block's candidates some lane hit
       for (uint64_t bits = bits0; bits; bits &= bits - 1) {
         const int src = __builtin_ctzll(bits);
         if constexpr (MODE == CAND_MARK) {
-          const bool h = fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src));
-          hit_mine = lane == src ? h : hit_mine;
+          if (fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src))) hits |= 1ull << src;
         } else {
           fn(__builtin_amdgcn_readlane(id, src), gauss_from_lane(mine, src));
         }
       }
-      if (MODE == CAND_MARK && !use_marks && keep) M.order[e] = o | (hit_mine ? kOrderMark : 0);
+      if (MODE == CAND_MARK && !use_marks && keep)
+        M.order[e] = o | (((hits >> lane) & 1ull) ? kOrderMark : 0);
     }
   } else {
     for (int e = 0; e < n_active; e++) fn(e, with_origin(load_gauss(s.geom, e), ox, oy, oz));
