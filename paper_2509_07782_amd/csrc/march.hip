@@ -561,6 +561,7 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
       hi = best <= lo ? -kInf : fminf(hi, best);
     }
   };
+  __builtin_amdgcn_s_setprio(3);   // a dependent walk, as the collection's
   if (ballot(search) == 0) {
     // every pending lane replays
   } else if (op.brute_force) {
@@ -620,6 +621,7 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
       else { leaf(~link[0]); node = -1; }
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   if (ss.pending) {
     if (replayed) best = rbest;
     else if (op.replay_mode == 1 && qn < kReplayK) op.replay[ray * kReplayK + qn] = best;
@@ -1593,7 +1595,12 @@ __device__ __forceinline__ int collect(const SceneDev &s, const MarchOpts &op, W
     R.cur = next;
     return cnt;
   }
+  // the walk is a chain of dependent loads and short bursts of work: while
+  // it runs, the wave's instructions issue ahead of other waves' long
+  // arithmetic runs on the same SIMD (wave priority, not a queue priority)
+  __builtin_amdgcn_s_setprio(3);
   const int cnt = trav_run(s, M, r, lane, t, n_active, stats, err, nodes, leaves, cyc_excl);
+  __builtin_amdgcn_s_setprio(0);
   if (op.replay_mode == 1) rec_put(R, op, M, t, cnt, lane);
   *start = R.cur;
   return cnt;
