@@ -333,7 +333,9 @@ def side_measurements(reps):
       step, graph-captured: steps/s;
     - 5M Gaussians, 16 views of mixed size: the graph-captured training step
       over one persistent launch (autotuned knobs), against the plain forward
-      of the 16 views launched one by one."""
+      of the 16 views launched one by one; and one GPU's share of that step
+      with the views sharded over 8 GPUs (2 views, forward + backward on the
+      whole scene) with the size of the gradient buffer to be summed."""
     import torch
     from paper_2509_07782_amd import autotune, inputs
     from paper_2509_07782_amd.render import Adam, RenderOptions, Renderer, TrainStep
@@ -434,6 +436,27 @@ def side_measurements(reps):
                      lr=0.0)
     ms_graph = _timed(step.replay, reps)
     r.check_errors()
+    # one GPU's share of the step when the 16 views are sharded over 8 GPUs
+    # (2 views, the full 5M scene and structure): forward + backward; the
+    # gradient buffer is what the one collective of that layout would sum
+    share = cams[:2]
+    Rs = sum(c.width * c.height for c in share)
+    pd = {k: v.detach() for k, v in p.items()}
+    gC = torch.full((Rs, 3), 1e-3, device="cuda")
+    st = r.new_state()
+
+    def share_step():
+        rgb, T = r.forward(share, tuned, state=st)
+        r.backward(st, rgb, T, gC, None, pd)
+
+    ms_share = _timed(share_step, reps)
+    st.close()
+    r.check_errors()
+    n5 = int(sc["means"].shape[0])
+    out["workload5_share_of_8"] = {
+        "views": len(share), "rays": Rs, "ms_fwd_bwd": ms_share,
+        "fwd_bwd_mrays_s": Rs / (ms_share * 1e-3) / 1e6,
+        "gradient_buffer_bytes": n5 * 4 * (3 + 3 + 4 + 1 + 3 * (sc["sh_degree"] + 1) ** 2)}
     out["workload5"] = {"rays": R,
                         "graph_fwd_bwd_step_mrays_s": R / (ms_graph * 1e-3) / 1e6,
                         "batched_fwd_mrays_s": R / (ms_tuned_fwd * 1e-3) / 1e6,
