@@ -72,7 +72,7 @@ def source_hash():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
