@@ -135,17 +135,27 @@ __device__ __forceinline__ Chord chord(const Gauss &g, const Ray &r) {
 // Colour of a Gaussian at the lane's direction: c = sum_m f_m Y_m.  Every
 // colour record is kColFloats long whatever the degree (zero past 3 sh_k) and
 // Y_m = 0 for m >= sh_k, so the record is read at fixed offsets, without
-// branches, and the terms past the degree add exact zeros.
-__device__ __forceinline__ void colour(const float *col, int j, const float *Y, float &cr,
-                                       float &cg, float &cb) {
-  cfloat4p p = as_const4(col) + (size_t)(kColFloats / 4) * j;
+// branches, and the terms past the degree add exact zeros.  The record's
+// three 64-byte scalar loads (colour_load) can be issued ahead of work that
+// does not need them, so that their latency overlaps it (colour_eval).
+struct ColRec {
   vf4 f[kColFloats / 4];
+};
+
+__device__ __forceinline__ ColRec colour_load(const float *col, int j) {
+  cfloat4p p = as_const4(col) + (size_t)(kColFloats / 4) * j;
+  ColRec c;
 #pragma unroll
-  for (int q = 0; q < kColFloats / 4; q++) f[q] = p[q];
+  for (int q = 0; q < kColFloats / 4; q++) c.f[q] = p[q];
+  return c;
+}
+
+__device__ __forceinline__ void colour_eval(const ColRec &rc, const float *Y, float &cr, float &cg,
+                                            float &cb) {
   float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int q = 0; q < kColFloats / 4; q++) {
-    const float fv[4] = {f[q].x, f[q].y, f[q].z, f[q].w};
+    const float fv[4] = {rc.f[q].x, rc.f[q].y, rc.f[q].z, rc.f[q].w};
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       const int flat = 4 * q + e;
@@ -153,6 +163,11 @@ __device__ __forceinline__ void colour(const float *col, int j, const float *Y, 
     }
   }
   cr = acc[0]; cg = acc[1]; cb = acc[2];
+}
+
+__device__ __forceinline__ void colour(const float *col, int j, const float *Y, float &cr,
+                                       float &cg, float &cb) {
+  colour_eval(colour_load(col, j), Y, cr, cg, cb);
 }
 
 // Spherical-Gaussian lobes of Gaussian j added to the lane's colour:
@@ -1834,9 +1849,10 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
                                       [&](int j, const Gauss &g) {
         const bool want = go;
         if (stats) cnt[ST_CAND]++;
-        if (ballot(want) == 0) return false;
         const Chord c = chord(g, r);
-        const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
+        // one conjunction, not a chain of short-circuit branches: the test
+        // stays in lane masks, and the wave's ballot of it is one mask and
+        const bool hit = want & c.exists & (c.tin <= hi) & (c.tout >= lo);
         if (ballot(hit) == 0) return false;
         if (stats) cnt[ST_CAND_HIT]++;
         if (hit) {
@@ -1849,11 +1865,14 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
             }
             n_dump++;
           }
-          float cr, cg, cb;
-          colour(s.col, j, Y, cr, cg, cb);
-          if constexpr (SG) sg_colour(s.sg, j, r.dx, r.dy, r.dz, cr, cg, cb);
+          // the colour record's loads go out before the sample weights,
+          // which do not need them
+          const ColRec rc = colour_load(s.col, j);
           float wk[NS];
           const uint32_t live = sample_weights<NS, true>(g, c, sp, wk);
+          float cr, cg, cb;
+          colour_eval(rc, Y, cr, cg, cb);
+          if constexpr (SG) sg_colour(s.sg, j, r.dx, r.dy, r.dz, cr, cg, cb);
 #pragma unroll
           for (int k = 0; k < NS; k++) {
             if (!(live & (1u << k))) continue;
@@ -1885,7 +1904,6 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r,
                            [&](int j, const Gauss &g) {
           const bool want = empty;
-          if (ballot(want) == 0) return;
           const Chord c = chord(g, r);
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
         });
@@ -2096,9 +2114,8 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
         for_each_candidate<CAND_MARK>(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r,
                                       [&](int j, const Gauss &g) {
         const bool want = go;
-        if (ballot(want) == 0) return false;
         const Chord c = chord(g, r);
-        const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
+        const bool hit = want & c.exists & (c.tin <= hi) & (c.tout >= lo);
         if (ballot(hit) == 0) return false;
         if (hit) {
           nhit++;
@@ -2153,11 +2170,10 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
       if (ballot(any) != 0) {
         auto pass_b = [&](int j, const Gauss &g) {
           const bool want = any;
-          if (ballot(want) == 0) return;
           float opx, opy, opz, dpx, dpy, dpz;
           ray_local(g, r, opx, opy, opz, dpx, dpy, dpz);
           const Chord c = chord(g, r);
-          const bool hit = want && c.exists && c.tin <= hi && c.tout >= lo;
+          const bool hit = want & c.exists & (c.tin <= hi) & (c.tout >= lo);
           if (ballot(hit) == 0) return;
           float S = 0.0f;
           float v[16];
@@ -2261,7 +2277,6 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
         for_each_candidate(SRC_LIST, s, M, win.count, lane, bmin, kInf, n_active, r,
                            [&](int j, const Gauss &g) {
           const bool want = empty;
-          if (ballot(want) == 0) return;
           const Chord c = chord(g, r);
           if (want && c.exists && c.tout >= b && c.tin <= win.hi) best = fminf(best, fmaxf(c.tin, b));
         });
