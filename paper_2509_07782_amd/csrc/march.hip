@@ -219,6 +219,16 @@ struct WaveStack {
   }
 };
 
+// Ends the compiler's freedom to sink a load towards its first use: the
+// value must be in registers here, so loads written together are issued
+// together and waited for once (empty asm statements, no instruction).
+// pin_loaded: a per-lane (vector) value; pin_uniform: a wave-uniform one
+// from the scalar cache.
+__device__ __forceinline__ void pin_loaded(const vf4 &x) {
+  asm volatile("" : : "v"(x.x), "v"(x.y), "v"(x.z), "v"(x.w));
+}
+__device__ __forceinline__ void pin_uniform(float x) { asm volatile("" : : "s"(x)); }
+
 // ---------------------------------------------------------------------------
 // Work distribution: global tile index -> view, pixel, output ray.
 
@@ -603,17 +613,28 @@ __device__ __forceinline__ void closest_pass(const SceneDev &s, const MarchOpts 
         const vf4 x = np[q];
         f[4 * q] = x.x; f[4 * q + 1] = x.y; f[4 * q + 2] = x.z; f[4 * q + 3] = x.w;
       }
+      // the boxes and links go out as one batch of loads: the box tests and
+      // the link checks below would otherwise each wait for a load of their
+      // own
+#pragma unroll
+      for (int q = 0; q < 24 + 4; q++) pin_uniform(f[q]);
       int link[4];
       float e[4];
-      bool bad = false;
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         link[k] = __float_as_int(f[24 + k]);
-        const bool valid = link[k] != kNoChild;
-        bad = bad || (valid && (link[k] >= 0 ? link[k] >= n_inner : ~link[k] >= n_active));
-        e[k] = valid ? wave_min_nonneg_dpp(box_entry(f[6 * k], f[6 * k + 1], f[6 * k + 2], f[6 * k + 3],
-                                              f[6 * k + 4], f[6 * k + 5], r, lo, hi))
-                     : kInf;
+        e[k] = link[k] != kNoChild
+                   ? wave_min_nonneg_dpp(box_entry(f[6 * k], f[6 * k + 1], f[6 * k + 2], f[6 * k + 3],
+                                                   f[6 * k + 4], f[6 * k + 5], r, lo, hi))
+                   : kInf;
+      }
+      // links out of range (a malformed tree) end the walk; checked after
+      // the box tests, which do not need them, in one branch-free test
+      int bad = 0;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const int lk = link[k];
+        bad |= (lk != kNoChild) & (lk >= 0 ? lk >= n_inner : ~lk >= n_active);
       }
       if (bad) { if (err) *err = 3; break; }
       // nearest child next; the others on the stack, farthest first (the
@@ -1190,11 +1211,19 @@ __device__ __forceinline__ int trav_run(const SceneDev &s, WaveMem &M, const Ray
       if (test) {
         const vf4 *gp = reinterpret_cast<const vf4 *>(s.geom) + 4 * j;
         const vf4 g0 = gp[0], g3 = gp[3];
+        // the support-function record is fetched with the geometry, before
+        // the sphere test decides whether it is needed: one memory round
+        // trip per batch of leaves instead of two
+        vf4 x0 = {0.0f, 0.0f, 0.0f, 0.0f}, x1 = x0;
+        if (cone.narrow) {
+          const vf4 *ap = reinterpret_cast<const vf4 *>(s.aux) + 2 * j;
+          x0 = ap[0];
+          x1 = ap[1];
+        }
+        pin_loaded(g0); pin_loaded(g3); pin_loaded(x0); pin_loaded(x1);
         const float vx = g0.x - self.ox, vy = g0.y - self.oy, vz = g0.z - self.oz;
         keep = cone_sphere(cone, vx, vy, vz, g3.w, &tmin, &tmax);
         if (keep && cone.narrow) {
-          const vf4 *ap = reinterpret_cast<const vf4 *>(s.aux) + 2 * j;
-          const vf4 x0 = ap[0], x1 = ap[1];
           float lo, hi;
           const bool in_cone = support_bounds(cone, vx, vy, vz, sqrtf(g0.w), x0.x, x0.y, x0.z,
                                               x0.w, x1.x, x1.y, x1.z, &lo, &hi);
@@ -1318,10 +1347,13 @@ __device__ __forceinline__ void for_each_candidate(int kind, const SceneDev &s, 
       if (e < count) {
         const int om = M.order[e];
         o = om & (kOrderMark - 1);
-        keep = !(M.l_tin[o] > b_max) && !(M.l_tout[o] < a_min);
-        if (MODE == CAND_FILTER || (MODE == CAND_MARK && use_marks))
-          keep = keep && (om & kOrderMark) != 0;
+        // the entry's three words are read together (no short-circuit
+        // between the depth tests, which would wait for each read in turn)
+        const float tin = M.l_tin[o], tout = M.l_tout[o];
         id = M.l_id[o];
+        keep = !(tin > b_max) & !(tout < a_min);
+        if (MODE == CAND_FILTER || (MODE == CAND_MARK && use_marks))
+          keep = keep & ((om & kOrderMark) != 0);
       }
       const uint64_t bits0 = ballot(keep);
       if (!bits0) continue;
