@@ -1116,15 +1116,19 @@ __device__ __forceinline__ int trav_run(const SceneDev &s, WaveMem &M, const Ray
       const int cr = live ? __float_as_int(b.w) : kNoChild;
       const int nlo = __float_as_int(c.w), nhi = __float_as_int(d.w);
       const int gamma = cl < 0 ? ~cl : cl;       // left range [nlo, gamma], right [gamma+1, nhi]
-      const bool bad = live && ((cl >= 0 ? cl >= n_inner : ~cl >= n_active) ||
-                                (cr != kNoChild && ((cr >= 0 ? cr >= n_inner : ~cr >= n_active) ||
-                                                    !(0 <= nlo && nlo <= gamma && gamma < nhi &&
-                                                      nhi < n_active))));
+      // validity of the links and ranges (a malformed tree ends the walk),
+      // then the Z-range and packet tests: plain conjunctions, so that they
+      // stay in lane masks instead of branching on every term
+      const bool badL = cl >= 0 ? cl >= n_inner : ~cl >= n_active;
+      const bool badR = (cr != kNoChild) &
+                        ((cr >= 0 ? cr >= n_inner : ~cr >= n_active) |
+                         !((0 <= nlo) & (nlo <= gamma) & (gamma < nhi) & (nhi < n_active)));
+      const bool bad = live & (badL | badR);
       if (ballot(bad)) { if (err) *err = 3; t.count = 0; t.sp = 0; t.staged = 0; return -1; }
-      const bool inL = live && nlo < z1 && gamma >= z0;
-      const bool inR = live && cr != kNoChild && gamma + 1 < z1 && nhi >= z0;
-      const bool hL = inL && cone_box(cone, self, a.x, a.y, a.z, b.x, b.y, b.z);
-      const bool hR = inR && cone_box(cone, self, c.x, c.y, c.z, d.x, d.y, d.z);
+      const bool inL = live & (nlo < z1) & (gamma >= z0);
+      const bool inR = live & (cr != kNoChild) & (gamma + 1 < z1) & (nhi >= z0);
+      const bool hL = inL & cone_box(cone, self, a.x, a.y, a.z, b.x, b.y, b.z);
+      const bool hR = inR & cone_box(cone, self, c.x, c.y, c.z, d.x, d.y, d.z);
       // children, in lane order, left before right
       bool lI = hL && cl >= 0, rI = hR && cr >= 0;
       const bool lL = hL && cl < 0, rL = hR && cr < 0;
