@@ -413,6 +413,15 @@ __device__ __forceinline__ float swap16_sum(float a, float b) {
                                                   false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
+__device__ __forceinline__ float uniform_lane(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+// In-row DPP permute of x; a lane with no valid source keeps `id`.
+template <int CTRL>
+__device__ __forceinline__ float dpp_or(float x, float id) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(id), __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
@@ -546,15 +555,28 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return uniform_float(v);
 }
+// Wave minimum and maximum (exact, so the order of the reduction does not
+// matter) without LDS traffic: four in-row DPP permutes (quad xor 1, quad
+// xor 2, half-row mirror, row mirror) leave each row's extreme in every lane
+// of the row, and the four rows are read out.  Called with the whole wave
+// active.
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return uniform_float(v);
+  v = fminf(v, dpp_or<0xb1>(v, kInf));
+  v = fminf(v, dpp_or<0x4e>(v, kInf));
+  v = fminf(v, dpp_or<0x141>(v, kInf));
+  v = fminf(v, dpp_or<0x140>(v, kInf));
+  const float a = fminf(uniform_lane(v, 0), uniform_lane(v, 16));
+  const float b = fminf(uniform_lane(v, 32), uniform_lane(v, 48));
+  return fminf(a, b);
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return uniform_float(v);
+  v = fmaxf(v, dpp_or<0xb1>(v, -kInf));
+  v = fmaxf(v, dpp_or<0x4e>(v, -kInf));
+  v = fmaxf(v, dpp_or<0x141>(v, -kInf));
+  v = fmaxf(v, dpp_or<0x140>(v, -kInf));
+  const float a = fmaxf(uniform_lane(v, 0), uniform_lane(v, 16));
+  const float b = fmaxf(uniform_lane(v, 32), uniform_lane(v, 48));
+  return fmaxf(a, b);
 }
 
 // Closest hit (Alg. 1 ClosestHit, Eq. 4) for the lanes with `pending` set:
@@ -2216,9 +2238,9 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
 #pragma unroll
           for (int e2 = 0; e2 < 16; e2++) v[e2] = 0.0f;
           if (hit) {
-            // everything that needs the geometry record first, so that its
-            // (uniform) registers are free again before the colour record
-            // is loaded
+            // the colour record's loads go out first: the sample weights and
+            // the geometry terms below do not need them
+            const ColRec rc = colour_load(s.col, j);
             float wk[NS];
             sample_weights<NS>(g, c, sp, wk);
             // closest-approach point in the local frame, and its world
@@ -2229,7 +2251,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
                                  fmaf(c.ts, r.dz, r.oz - g.mz)};
             const float inv_sig = __builtin_amdgcn_rcpf(g.sig);
             float cr, cg, cb;
-            colour(s.col, j, Y, cr, cg, cb);
+            colour_eval(rc, Y, cr, cg, cb);
             if constexpr (SG) sg_colour(s.sg, j, r.dx, r.dy, r.dz, cr, cg, cb);
             const float gc = fmaf(Gc0, cr, fmaf(Gc1, cg, Gc2 * cb));
             // dL/dw_k = dsigma_k + G.c_l T_k phi_k; dq_k = -w_k dL/dw_k / 2
