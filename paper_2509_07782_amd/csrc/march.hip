@@ -147,6 +147,10 @@ __device__ __forceinline__ ColRec colour_load(const float *col, int j) {
   ColRec c;
 #pragma unroll
   for (int q = 0; q < kColFloats / 4; q++) c.f[q] = p[q];
+  // a scheduling barrier: the compiler would otherwise place the loads
+  // just before their first use, and their latency would not overlap the
+  // caller's work between colour_load and colour_eval
+  __builtin_amdgcn_sched_barrier(0);
   return c;
 }
 
