@@ -1913,7 +1913,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         if (stats) cnt[ST_CAND]++;
         const Chord c = chord(g, r);
         // one conjunction, not a chain of short-circuit branches: the test
-        // stays in lane masks, and the wave's ballot of it is one mask and
+        // stays in lane masks, with no branch per term
         const bool hit = want & c.exists & (c.tin <= hi) & (c.tout >= lo);
         if (ballot(hit) == 0) return false;
         if (stats) cnt[ST_CAND_HIT]++;
