@@ -232,6 +232,7 @@ __device__ __forceinline__ void pin_loaded(const vf4 &x) {
   asm volatile("" : : "v"(x.x), "v"(x.y), "v"(x.z), "v"(x.w));
 }
 __device__ __forceinline__ void pin_uniform(float x) { asm volatile("" : : "s"(x)); }
+__device__ __forceinline__ void pin_lane(uint32_t x) { asm volatile("" : : "v"(x)); }
 
 // ---------------------------------------------------------------------------
 // Work distribution: global tile index -> view, pixel, output ray.
@@ -1555,8 +1556,14 @@ __device__ __forceinline__ bool rec_get_samples(WinRec &R, const MarchOpts &op, 
     return false;
   }
   const uint32_t *p = op.wrec + off;
-  const uint64_t hm = ((uint64_t)(uint32_t)uniform_int((int)p[2]) << 32) | (uint32_t)uniform_int((int)p[1]);
-  const uint64_t em = ((uint64_t)(uint32_t)uniform_int((int)p[4]) << 32) | (uint32_t)uniform_int((int)p[3]);
+  // the header's five words in one batch of loads
+  uint32_t hw[kSrecHeader];
+#pragma unroll
+  for (int i = 0; i < kSrecHeader; i++) hw[i] = p[i];
+#pragma unroll
+  for (int i = 0; i < kSrecHeader; i++) pin_lane(hw[i]);
+  const uint64_t hm = ((uint64_t)(uint32_t)uniform_int((int)hw[2]) << 32) | (uint32_t)uniform_int((int)hw[1]);
+  const uint64_t em = ((uint64_t)(uint32_t)uniform_int((int)hw[4]) << 32) | (uint32_t)uniform_int((int)hw[3]);
   const int nh = __popcll(hm), ne = __popcll(em);
   if ((hm | em) != ballot(go) || (hm & em) != 0 ||
       !rec_fits(op, off, kSrecHeader + 4 * (uint64_t)NS * nh + ne)) {
@@ -1564,17 +1571,23 @@ __device__ __forceinline__ bool rec_get_samples(WinRec &R, const MarchOpts &op, 
     R.cur = kWrecNone;
     return false;
   }
-  R.cur = (uint32_t)uniform_int((int)p[0]);
+  R.cur = (uint32_t)uniform_int((int)hw[0]);
   const float *q = reinterpret_cast<const float *>(p + kSrecHeader);
   const uint64_t below = lanes_below(lane);
   const bool hit = (hm >> lane) & 1ull;
   if (hit) {
     const int rk = __popcll(hm & below);
+    // the 4 N_s values in one batch of loads (the compiler would otherwise
+    // wait for every few of them in turn to keep fewer registers live)
+    float v[4 * NS];
+#pragma unroll
+    for (int i = 0; i < 4 * NS; i++) v[i] = q[i * nh + rk];
+#pragma unroll
+    for (int i = 0; i < 4 * NS; i++) pin_lane(__float_as_uint(v[i]));
 #pragma unroll
     for (int k = 0; k < NS; k++) {
-      sg[k] = q[(4 * k) * nh + rk];
-      GW[k] = fmaf(Gc0, q[(4 * k + 1) * nh + rk],
-                   fmaf(Gc1, q[(4 * k + 2) * nh + rk], Gc2 * q[(4 * k + 3) * nh + rk]));
+      sg[k] = v[4 * k];
+      GW[k] = fmaf(Gc0, v[4 * k + 1], fmaf(Gc1, v[4 * k + 2], Gc2 * v[4 * k + 3]));
     }
   }
   if ((em >> lane) & 1ull) *best = q[4 * NS * nh + __popcll(em & below)];
@@ -1613,18 +1626,30 @@ __device__ __forceinline__ bool rec_load_marks(const MarchOpts &op, WaveMem &M, 
   const int words = (count + 63) >> 6;
   if (!rec_fits(op, off, 2 + 2 * (uint64_t)words)) { *next = kWrecNone; return false; }
   const uint32_t *p = op.wrec + off;
-  if (uniform_int((int)p[1]) != count) { *next = kWrecNone; return false; }
+  const uint32_t h0 = p[0], h1 = p[1];
+  pin_lane(h0); pin_lane(h1);
+  constexpr int kSlots = kListCap / 64;
+  if (uniform_int((int)h1) != count || words > kSlots) { *next = kWrecNone; return false; }
   __builtin_amdgcn_wave_barrier();
-  for (int q = 0; q < words; q++) {
-    const int e = 64 * q + lane;
-    const uint32_t w = p[2 + 2 * q + (lane >> 5)];
-    if (e < count) {
-      const int o = M.order[e] & (kOrderMark - 1);
-      M.order[e] = o | (((w >> (lane & 31)) & 1u) ? kOrderMark : 0);
+  if (words > 0) {
+    // every mark word in one batch of loads (slots past the end read the
+    // last word again and are not used)
+    uint32_t w[kSlots];
+#pragma unroll
+    for (int q = 0; q < kSlots; q++) w[q] = p[2 + 2 * min(q, words - 1) + (lane >> 5)];
+#pragma unroll
+    for (int q = 0; q < kSlots; q++) pin_lane(w[q]);
+#pragma unroll
+    for (int q = 0; q < kSlots; q++) {
+      const int e = 64 * q + lane;
+      if (q < words && e < count) {
+        const int o = M.order[e] & (kOrderMark - 1);
+        M.order[e] = o | (((w[q] >> (lane & 31)) & 1u) ? kOrderMark : 0);
+      }
     }
   }
   __builtin_amdgcn_wave_barrier();
-  *next = (uint32_t)uniform_int((int)p[0]);
+  *next = (uint32_t)uniform_int((int)h0);
   return true;
 }
 
