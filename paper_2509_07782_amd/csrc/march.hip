@@ -1673,11 +1673,15 @@ __device__ __forceinline__ bool rec_next_marks(WinRec &R, const MarchOpts &op, W
 // One collection: the tree walk (recorded in a recording forward) or, in a
 // replaying backward of a complete tile, the recorded chunk and state.
 // *start receives the chunk's record offset.
+// REPLAY false (the forward kernel) compiles the replay branch out: a
+// forward never reads a record, and the branch's registers would count
+// against the whole kernel.
+template <bool REPLAY>
 __device__ __forceinline__ int collect(const SceneDev &s, const MarchOpts &op, WaveMem &M,
                                        const Ray &r, int lane, Trav &t, int n_active, bool stats,
                                        int32_t *err, int32_t &nodes, int32_t &leaves,
                                        int64_t *cyc_excl, WinRec &R, uint32_t *start) {
-  if (op.replay_mode == 2 && R.ok) {
+  if (REPLAY && op.replay_mode == 2 && R.ok) {
     if (R.cur == kWrecNone || !rec_fits(op, R.cur, kWrecHeader)) {   // a broken record
       if (err) *err = 5;
       t.count = 0;
@@ -1725,6 +1729,7 @@ struct Window {
 // no live lane can, collects a new window for all live lanes.  A window that
 // could not be collected whole serves the current segment only, chunk by
 // chunk.
+template <bool REPLAY>
 __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts &op, WaveMem &M,
                                               const Ray &r, int lane, int n_active, bool alive,
                                               float a, float b, Window &w, bool stats,
@@ -1749,8 +1754,8 @@ __device__ __forceinline__ void ensure_window(const SceneDev &s, const MarchOpts
   windows++;
   trav_start(M, lane, w.t, rays, 0, n_active);
   w.zend = n_active;
-  const int cnt = collect(s, op, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl, R,
-                          &w.rec_first);
+  const int cnt = collect<REPLAY>(s, op, M, r, lane, w.t, n_active, stats, err, nodes, leaves,
+                                  cyc_excl, R, &w.rec_first);
   w.rec_last = w.rec_first;
   w.kind = SRC_LIST;
   w.count = cnt > 0 ? cnt : 0;   // a malformed tree ends the rays (error flag set)
@@ -1786,6 +1791,7 @@ __device__ __forceinline__ void first_chunk(const SceneDev &s, WaveMem &M, const
 // paused collection, or after a cut at z1 collects again from z1 for the
 // lanes in `lanes` over their segments [a, b].  False when the segment's
 // candidates are exhausted.
+template <bool REPLAY>
 __device__ __forceinline__ bool next_chunk(const SceneDev &s, const MarchOpts &op, WaveMem &M,
                                            const Ray &r, int lane, int n_active, bool lanes,
                                            float a, float b, Window &w, bool stats, int32_t *err,
@@ -1793,7 +1799,7 @@ __device__ __forceinline__ bool next_chunk(const SceneDev &s, const MarchOpts &o
                                            WinRec &R, int64_t *cyc_excl = nullptr) {
   if (!w.chunked) return false;
   if (w.t.paused) {
-    if (!(op.replay_mode == 2 && R.ok)) trav_advance(M, lane, w.t);
+    if (!(REPLAY && op.replay_mode == 2 && R.ok)) trav_advance(M, lane, w.t);
   } else {
     if (w.t.z1 >= w.zend) return false;
     const uint64_t rays = ballot(lanes);
@@ -1803,8 +1809,8 @@ __device__ __forceinline__ bool next_chunk(const SceneDev &s, const MarchOpts &o
     windows++;
     trav_start(M, lane, w.t, rays, w.t.z1, w.zend);
   }
-  const int cnt = collect(s, op, M, r, lane, w.t, n_active, stats, err, nodes, leaves, cyc_excl, R,
-                          &w.rec_last);
+  const int cnt = collect<REPLAY>(s, op, M, r, lane, w.t, n_active, stats, err, nodes, leaves,
+                                  cyc_excl, R, &w.rec_last);
   if (cnt < 0) {
     w.count = 0;
     w.chunked = false;
@@ -1919,7 +1925,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
       if (!ss.alive) { sp.t0 = 0.0f; sp.dt = 0.0f; }
       bool go;
       if (stats) cyc_t0 = clock64();
-      ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
+      ensure_window<false>(s, op, M, r, lane, n_active, ss.alive, a, b, win, stats, ls.error_flag,
                     cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS], go, rec,
                     stats ? &cyc_boxstat : nullptr);
       if (stats) cyc_collect += clock64() - cyc_t0;
@@ -1975,7 +1981,7 @@ __global__ __launch_bounds__(kWave, NS <= 8 ? 3 : 2) void k_forward(SceneDev s, 
         if (op.replay_mode == 1 && win.kind == SRC_LIST) rec_put_marks(rec, op, M, win.count, lane);
       } while ([&] {
         if (stats) cyc_t0 = clock64();
-        const bool more = next_chunk(s, op, M, r, lane, n_active, go, a, b, win, stats,
+        const bool more = next_chunk<false>(s, op, M, r, lane, n_active, go, a, b, win, stats,
                                      ls.error_flag, cnt[ST_NODES], cnt[ST_LEAVES], cnt[ST_WINDOWS],
                                      rec, stats ? &cyc_boxstat : nullptr);
         if (stats) cyc_collect += clock64() - cyc_t0;
@@ -2180,7 +2186,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
       }
       if (!ss.alive) { sp.t0 = 0.0f; sp.dt = 0.0f; }
       bool go;
-      ensure_window(s, op, M, r, lane, n_active, ss.alive, a, b, win, false, ls.error_flag,
+      ensure_window<true>(s, op, M, r, lane, n_active, ss.alive, a, b, win, false, ls.error_flag,
                     dummy_nodes, dummy_leaves, dummy_windows, go, rec);
       const float a_min = wave_min(go ? a : kInf), b_max = wave_max(go ? b : -kInf);
       const float lo = go ? a : kInf, hi = go ? b : -kInf;
@@ -2220,7 +2226,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
         }
         return true;
       }, use_marks);
-      } while (next_chunk(s, op, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
+      } while (next_chunk<true>(s, op, M, r, lane, n_active, go, a, b, win, false, ls.error_flag,
                             dummy_nodes, dummy_leaves, dummy_windows, rec));
       float best = kInf;
       if (from_rec)
@@ -2351,7 +2357,7 @@ __global__ __launch_bounds__(kWave, 2) void k_backward(SceneDev s, ViewTable vt,
           first_chunk(s, M, r, lane, n_active, any, a, b, zlast, win, false, ls.error_flag,
                       dummy_nodes, dummy_leaves, dummy_windows);
           do for_each_candidate(win.kind, s, M, win.count, lane, a_min, b_max, n_active, r, pass_b);
-          while (next_chunk(s, op, M, r, lane, n_active, any, a, b, win, false, ls.error_flag,
+          while (next_chunk<true>(s, op, M, r, lane, n_active, any, a, b, win, false, ls.error_flag,
                             dummy_nodes, dummy_leaves, dummy_windows, rec));
         }
       }
